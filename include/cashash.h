@@ -1,0 +1,184 @@
+/*
+ * cashash.h -- C ABI of the MI355X (gfx950) Cascade Hashing matcher.
+ *
+ * The library computes, for 128-d uint8 SIFT descriptors, the hot path of
+ * GPU-accelerated Cascade Hashing image matching (Xu, Sun, Tao, "GPU
+ * Accelerated Cascade Hashing Image Matching for Large Scale 3D
+ * Reconstruction"):
+ *   - hashing codes: Charikar sign random projections of mean-centred
+ *     descriptors ("The Improved Parallel Calculation of Hashing Code"),
+ *     128-bit remapping codes (Step 2, n = 128) and six 8-bit lookup keys
+ *     (Step 1, m = 8, multiple tables);
+ *   - matching of a query image I against a train image J ("Review of
+ *     Cascade Hashing", Steps 1-4): union of same-key candidates over the
+ *     tables, Hamming ranking to the top k, exact squared Euclidean distance
+ *     ("Improved Parallel Euclidean Distance Calculation") and Lowe's ratio
+ *     test;
+ *   - the geometry-guided variant (Eq. 1-2): candidates restricted to a band
+ *     of max_px pixels around the query's epipolar line before ranking;
+ *   - the threshold tau of "Improved Parallel Hashing Ranking".
+ *
+ * Every step runs in hand-written HIP kernels on the current HIP device.
+ * No function throws; every int-returning function returns CASHASH_OK (0) or
+ * a negative error code, and cashash_last_error() gives the message.  On
+ * error the contents of output buffers are unspecified.
+ *
+ * Buffers.  The caller owns every buffer.  Arrays of per-image pointers
+ * (desc, codes, keys, kp) are host arrays; the pointers inside them, and the
+ * per-query output arrays, are device pointers when cfg.mem ==
+ * CASHASH_MEM_DEVICE and host pointers when cfg.mem == CASHASH_MEM_HOST (the
+ * library then streams images to the device in blocks it schedules under
+ * cfg.device_budget_bytes and copies results back).  The pair list and the
+ * fundamental matrices are always host memory.  Calls are synchronous: when
+ * a call returns, its outputs are complete.  The library keeps no pointer to
+ * caller memory after a call returns.  One context per host thread.
+ */
+#ifndef CASHASH_H
+#define CASHASH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CASHASH_OK 0
+#define CASHASH_E_INVAL (-1)          /* null pointer, bad size or bad index */
+#define CASHASH_E_NOMEM (-2)          /* device or pinned host allocation failed, or budget too small */
+#define CASHASH_E_DEVICE (-3)         /* a HIP call failed */
+#define CASHASH_E_UNSAFE_MATRIX (-4)  /* a projection row is too long for the fast-path margin proof */
+#define CASHASH_E_LIMIT (-5)          /* n_feat > 65535, k outside 1..64, or another hard limit */
+
+#define CASHASH_MODE_BATCHED_BF16X2 0      /* BF16 hi+lo MFMA projection; all pairs in one persistent launch */
+#define CASHASH_MODE_PLAIN_FP32_PER_PAIR 1 /* FP32 VALU projection; one launch set per image pair */
+
+#define CASHASH_MEM_HOST 0
+#define CASHASH_MEM_DEVICE 1
+
+#define CASHASH_DIM 128
+#define CASHASH_TABLES 6
+#define CASHASH_MAX_FEAT 65535
+#define CASHASH_MAX_K 64
+
+typedef struct {
+    int32_t k;                   /* Hamming-ranked candidates kept per query, 1..64 (default 10) */
+    int32_t ratio_num;           /* ratio test den^2 * D1 < num^2 * D2 on squared distances */
+    int32_t ratio_den;           /*   (default 4 / 5, i.e. 0.8); both > 0 */
+    int32_t max_hamming;         /* tau: candidates with Hamming distance > tau are dropped; 128 = off */
+    double margin_coef;          /* fast projection trusted iff |v| > margin_coef*|x| + 2^-20*|bias| + 2^-26;
+                                    otherwise recomputed in binary64 (default 1e-3) */
+    int32_t mode;                /* CASHASH_MODE_* */
+    int32_t mem;                 /* CASHASH_MEM_* : where image data and outputs live */
+    int64_t device_budget_bytes; /* host-memory mode: device bytes for resident images (0 = 1/4 of free) */
+    void* stream;                /* hipStream_t to run on, or NULL for a library-owned stream */
+} cashash_config;
+
+typedef struct {
+    int32_t n_images;
+    const uint8_t* const* desc; /* desc[m]: n_feat[m] x 128 uint8, row-major, row = feature index */
+    const int32_t* n_feat;      /* host array, 0..65535 per image */
+} cashash_images;
+
+typedef struct {
+    int64_t pairs, queries;
+    int64_t bucket_entries;         /* sum over queries of the six same-key bucket sizes */
+    int64_t union_size;             /* sum over queries of the candidate-set size (after the band) */
+    int64_t near_margin_recomputes; /* projections recomputed in binary64 */
+    int64_t h2d_bytes, d2h_bytes, image_loads;
+    double ms_codes, ms_match;      /* wall time of the call */
+} cashash_stats;
+
+/* Fill cfg with the defaults above. */
+void cashash_default_config(cashash_config* cfg);
+
+typedef struct cashash_ctx cashash_ctx; /* opaque: device buffers, streams, graphs, tuning */
+
+/* Create a context on the current HIP device.
+ * r_code: host float64 [128][128], row j gives code bit j.
+ * r_bucket: host float64 [6][8][128], row (t, b) gives bit b of key t.
+ * Both are copied.  cfg may be NULL (defaults).
+ * Errors: E_INVAL (null out / matrices, bad ratio or mode), E_LIMIT (k not in
+ * 1..64, max_hamming not in 0..128), E_UNSAFE_MATRIX (some row has
+ * 5e-5 * |row|_2 >= margin_coef, or a non-finite entry: the fast
+ * projection's rounding bound would not stay below the margin), E_DEVICE. */
+int cashash_create(cashash_ctx** out, const double* r_code, const double* r_bucket,
+                   const cashash_config* cfg);
+
+/* Replace the configuration (same checks as cashash_create). */
+int cashash_set_config(cashash_ctx* ctx, const cashash_config* cfg);
+
+/* Release every resource of ctx (NULL is a no-op). */
+void cashash_destroy(cashash_ctx* ctx);
+
+/* Codes and keys of every descriptor of the image set (the paper's hash-code
+ * module).  The mean used for centring is the mean over ALL descriptors of
+ * `images`.  Output per image m (buffers of the caller, on the side given by
+ * cfg.mem):
+ *   codes_out[m]: uint64 [n_feat[m]][2]; bit j (row j of r_code) is bit j&63
+ *                 of word j>>6; bit = [r_j . (x - mean) > 0], exact zero -> 0.
+ *   keys_out[m] : uint8 [n_feat[m]][6]; bit b of byte t is row (t, b).
+ * Every bit equals the sign of the binary64 fused multiply-add chain over
+ * components 0..127 of r_j . (N x - S), with S the column sums and N the
+ * descriptor count.  stats may be NULL. */
+int cashash_build_codes(cashash_ctx* ctx, const cashash_images* images,
+                        uint64_t* const* codes_out, uint8_t* const* keys_out, cashash_stats* stats);
+
+/* Match each (query image, train image) pair (Steps 1-4).
+ * codes / keys: as produced by cashash_build_codes for these images.
+ * pairs: host int32 [n_pairs][2] = (query, train); q == t is allowed.
+ * Outputs, flat over pairs: pair p occupies n_feat[pairs[p][0]] entries
+ * starting at the sum of n_feat[pairs[p'][0]] over p' < p.  Per query q:
+ *   match_idx: train index of the nearest kept candidate if the ratio test
+ *              passes, else -1 (fewer than two candidates never pass);
+ *   d1sq     : smallest squared Euclidean distance over the kept candidates,
+ *              -1 if none;
+ *   d2sq     : second smallest (counting multiplicity), -1 if fewer than two.
+ * Kept candidates: the k smallest (Hamming distance, train index) of the set
+ * union of the train points that share a key with q in any table, after
+ * dropping Hamming distance > max_hamming.  Ties in the nearest distance go
+ * to the smaller index.  stats may be NULL. */
+int cashash_match_pairs(cashash_ctx* ctx, const cashash_images* images,
+                        const uint64_t* const* codes, const uint8_t* const* keys,
+                        int64_t n_pairs, const int32_t* pairs,
+                        int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats);
+
+/* cashash_match_pairs with the epipolar constraint of Eq. 1-2 applied to the
+ * candidate set before ranking: candidate (x', y') of query (x, y) is kept iff
+ * e^2 <= max_px^2 (a^2 + b^2), where (a, b, c) = F (x, y, 1) and
+ * e = a x' + b y' + c, evaluated in binary64 without contraction in this
+ * order: a = (F0 x + F1 y) + F2, b = (F3 x + F4 y) + F5, c = (F6 x + F7 y) + F8,
+ * e = (a x' + b y') + c.
+ * kp_xy[m]: float32 [n_feat[m]][2] keypoints (side given by cfg.mem).
+ * F: host float64 [n_pairs][9] row-major.  max_px >= 0 and finite. */
+int cashash_match_pairs_epipolar(cashash_ctx* ctx, const cashash_images* images,
+                                 const uint64_t* const* codes, const uint8_t* const* keys,
+                                 const float* const* kp_xy, int64_t n_pairs, const int32_t* pairs,
+                                 const double* F, double max_px,
+                                 int32_t* match_idx, int32_t* d1sq, int32_t* d2sq,
+                                 cashash_stats* stats);
+
+/* Message for the last nonzero return on this thread ("" if none). */
+const char* cashash_last_error(void);
+
+/* Host logic of CASHASH_MEM_HOST matching, exposed for inspection and tests
+ * (no device call): plan the block schedule ("Three-Level Data Scheduling
+ * Strategy", matching subsection) for images of img_bytes[m] device bytes and
+ * the given pairs, with blocks of at most slot_bytes.  Images used by some
+ * pair are packed in index order into blocks; block pairs are visited as
+ * (i, i+1) .. (i, last), then (i, i), for i = 0, 1, ...; at most three blocks
+ * are resident.  Outputs: number of steps and blocks, block and image loads
+ * under that order, and optionally steps_out[4*s..] = (bi, bk, first, end)
+ * positions into order_out (n_pairs pair indices in visiting order).
+ * Errors: E_INVAL, E_NOMEM (an image alone exceeds slot_bytes). */
+int cashash_plan_schedule(int32_t n_images, const int64_t* img_bytes, int64_t n_pairs, const int32_t* pairs,
+                          int64_t slot_bytes, int64_t* n_steps, int64_t* n_blocks, int64_t* block_loads,
+                          int64_t* image_loads, int64_t* steps_out, int64_t max_steps, int64_t* order_out);
+
+/* Kernel-only timing of the last call's dominant kernel (the matcher), in
+ * milliseconds, measured with HIP events on the stream it ran on, and the
+ * number of launches it covered. */
+int cashash_last_kernel_ms(cashash_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

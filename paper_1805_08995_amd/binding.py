@@ -1,0 +1,251 @@
+"""ctypes binding of libcashash.so (include/cashash.h), argument marshalling only.
+
+Every step of the matching path runs in the library's HIP kernels.  PyTorch
+supplies device memory (tensors whose data pointers are passed through) and
+the stream (torch's current stream).  In host-memory mode numpy arrays are
+passed and the library streams them to the device itself.
+
+The library must have been built (``python -m paper_1805_08995_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcashash.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSAFE_MATRIX, E_LIMIT = 0, -1, -2, -3, -4, -5
+MODE_BATCHED_BF16X2, MODE_PLAIN_FP32_PER_PAIR = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+MODES = {"batched": MODE_BATCHED_BF16X2, "plain": MODE_PLAIN_FP32_PER_PAIR}
+MEMS = {"host": MEM_HOST, "device": MEM_DEVICE}
+EXPORTED = ["cashash_default_config", "cashash_create", "cashash_set_config", "cashash_destroy",
+            "cashash_build_codes", "cashash_match_pairs", "cashash_match_pairs_epipolar",
+            "cashash_last_error", "cashash_plan_schedule", "cashash_last_kernel_ms"]
+
+
+class Config(C.Structure):
+    _fields_ = [("k", C.c_int32), ("ratio_num", C.c_int32), ("ratio_den", C.c_int32),
+                ("max_hamming", C.c_int32), ("margin_coef", C.c_double), ("mode", C.c_int32),
+                ("mem", C.c_int32), ("device_budget_bytes", C.c_int64), ("stream", C.c_void_p)]
+
+
+class Images(C.Structure):
+    _fields_ = [("n_images", C.c_int32), ("desc", C.POINTER(C.c_void_p)), ("n_feat", C.POINTER(C.c_int32))]
+
+
+class Stats(C.Structure):
+    _fields_ = [("pairs", C.c_int64), ("queries", C.c_int64), ("bucket_entries", C.c_int64),
+                ("union_size", C.c_int64), ("near_margin_recomputes", C.c_int64),
+                ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("image_loads", C.c_int64),
+                ("ms_codes", C.c_double), ("ms_match", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class CashashError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cashash error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libcashash.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_08995_amd.build` "
+                              "(hipcc --offload-arch=gfx950); there is no fallback implementation")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.cashash_default_config.argtypes = [C.POINTER(Config)]
+        L.cashash_default_config.restype = None
+        L.cashash_create.argtypes = [C.POINTER(C.c_void_p), P, P, C.POINTER(Config)]
+        L.cashash_set_config.argtypes = [P, C.POINTER(Config)]
+        L.cashash_destroy.argtypes = [P]
+        L.cashash_destroy.restype = None
+        L.cashash_build_codes.argtypes = [P, C.POINTER(Images), P, P, C.POINTER(Stats)]
+        L.cashash_match_pairs.argtypes = [P, C.POINTER(Images), P, P, I64, P, P, P, P, C.POINTER(Stats)]
+        L.cashash_match_pairs_epipolar.argtypes = [P, C.POINTER(Images), P, P, P, I64, P, P, C.c_double,
+                                                   P, P, P, C.POINTER(Stats)]
+        L.cashash_last_error.restype = C.c_char_p
+        L.cashash_plan_schedule.argtypes = [I32, P, I64, P, I64, P, P, P, P, P, I64, P]
+        L.cashash_last_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for f in ("cashash_create", "cashash_set_config", "cashash_build_codes", "cashash_match_pairs",
+                  "cashash_match_pairs_epipolar", "cashash_plan_schedule", "cashash_last_kernel_ms"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != OK:
+        raise CashashError(rc, lib().cashash_last_error().decode())
+    return rc
+
+
+def default_config() -> Config:
+    c = Config()
+    lib().cashash_default_config(C.byref(c))
+    return c
+
+
+def _ptrs(vals):
+    return (C.c_void_p * max(1, len(vals)))(*vals)
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _dptr(t):
+    return t.data_ptr() if t.numel() else None
+
+
+def plan_schedule(img_bytes, pairs, slot_bytes, max_steps=None):
+    """Host-side block schedule (no device needed).  Returns a dict with the
+    step list [(bi, bk, begin, end)], visiting order and load counts."""
+    img_bytes = np.ascontiguousarray(img_bytes, np.int64)
+    pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+    out = [C.c_int64() for _ in range(4)]
+    n_max = max_steps if max_steps is not None else max(1, 2 * len(pairs) + 1)
+    steps = np.zeros((n_max, 4), np.int64)
+    order = np.zeros(max(1, len(pairs)), np.int64)
+    check(lib().cashash_plan_schedule(len(img_bytes), img_bytes.ctypes.data, len(pairs),
+                                      pairs.ctypes.data if len(pairs) else None, int(slot_bytes),
+                                      *[C.byref(o) for o in out], steps.ctypes.data, n_max,
+                                      order.ctypes.data))
+    n_steps = out[0].value
+    return {"steps": steps[:min(n_steps, n_max)], "n_steps": n_steps, "n_blocks": out[1].value,
+            "block_loads": out[2].value, "image_loads": out[3].value, "order": order[:len(pairs)]}
+
+
+class Matcher:
+    """A library context.  mem="device": images/codes/outputs are torch CUDA
+    tensors; mem="host": numpy arrays, streamed by the library."""
+
+    def __init__(self, r_code=None, r_bucket=None, *, k=10, ratio=(4, 5), max_hamming=128,
+                 margin_coef=1e-3, mode="batched", mem="device", device_budget_bytes=0, stream=None):
+        if r_code is None or r_bucket is None:
+            r_code, r_bucket = synth.projection_matrices()
+        self.r_code = np.ascontiguousarray(r_code, np.float64)
+        self.r_bucket = np.ascontiguousarray(r_bucket, np.float64)
+        if self.r_code.shape != (128, 128) or self.r_bucket.shape != (6, 8, 128):
+            raise ValueError("projection matrices must be [128,128] and [6,8,128]")
+        self.cfg = default_config()
+        self.cfg.k, self.cfg.ratio_num, self.cfg.ratio_den = int(k), int(ratio[0]), int(ratio[1])
+        self.cfg.max_hamming, self.cfg.margin_coef = int(max_hamming), float(margin_coef)
+        self.cfg.mode, self.cfg.mem = MODES[mode], MEMS[mem]
+        self.cfg.device_budget_bytes = int(device_budget_bytes)
+        self.mem = mem
+        if mem == "device" and stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self.cfg.stream = stream
+        h = C.c_void_p()
+        check(lib().cashash_create(C.byref(h), self.r_code.ctypes.data, self.r_bucket.ctypes.data,
+                                   C.byref(self.cfg)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cashash_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mode(self, mode):
+        self.cfg.mode = MODES[mode]
+        check(lib().cashash_set_config(self.h, C.byref(self.cfg)))
+
+    def last_kernel_ms(self):
+        ms, n = C.c_double(), C.c_int64()
+        check(lib().cashash_last_kernel_ms(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # ------------------------------------------------------------ marshalling
+    def _images(self, images):
+        nf = np.array([int(im.shape[0]) for im in images], np.int32)
+        if self.mem == "device":
+            ptrs = _ptrs([_dptr(im) for im in images])
+        else:
+            images = [np.ascontiguousarray(im, np.uint8) for im in images]
+            ptrs = _ptrs([im.ctypes.data if im.size else None for im in images])
+        st = Images(len(images), C.cast(ptrs, C.POINTER(C.c_void_p)), nf.ctypes.data_as(C.POINTER(C.c_int32)))
+        return st, (ptrs, nf, images)
+
+    def _arrays(self, arrs):
+        if self.mem == "device":
+            return _ptrs([_dptr(a) for a in arrs])
+        return _ptrs([a.ctypes.data if a.size else None for a in arrs])
+
+    def _alloc(self, n, shape_tail, dtype):
+        if self.mem == "device":
+            import torch
+            tdt = {np.uint64: torch.int64, np.uint8: torch.uint8, np.int32: torch.int32}[dtype]
+            return torch.empty((n, *shape_tail), dtype=tdt, device="cuda")
+        return np.zeros((n, *shape_tail), dtype)
+
+    def build_codes(self, images):
+        """Codes [n,2] (uint64 bits; int64 tensors on the device) and keys [n,6]
+        of every image, centred on the mean of the whole set."""
+        st, keep = self._images(images)
+        codes = [self._alloc(int(im.shape[0]), (2,), np.uint64) for im in images]
+        keys = [self._alloc(int(im.shape[0]), (6,), np.uint8) for im in images]
+        stats = Stats()
+        check(lib().cashash_build_codes(self.h, C.byref(st), self._arrays(codes), self._arrays(keys),
+                                        C.byref(stats)))
+        return codes, keys, stats.as_dict()
+
+    def _outputs(self, n, out):
+        if out is not None:
+            return out
+        return tuple(self._alloc(n, (), np.int32) for _ in range(3))
+
+    def match_pairs(self, images, codes, keys, pairs, out=None):
+        """(match_idx, d1sq, d2sq), flat over pairs in pair order."""
+        st, keep = self._images(images)
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if len(pairs) else 0
+        o = self._outputs(n, out)
+        stats = Stats()
+        check(lib().cashash_match_pairs(self.h, C.byref(st), self._arrays(codes), self._arrays(keys), len(pairs),
+                                        pairs.ctypes.data if len(pairs) else None,
+                                        *[(_dptr(a) if self.mem == "device" else (a.ctypes.data if a.size else None))
+                                          for a in o], C.byref(stats)))
+        return o, stats.as_dict()
+
+    def match_pairs_epipolar(self, images, codes, keys, kp, pairs, F, max_px, out=None):
+        st, keep = self._images(images)
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
+        if len(F) != len(pairs):
+            raise ValueError("one F per pair")
+        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if len(pairs) else 0
+        o = self._outputs(n, out)
+        stats = Stats()
+        check(lib().cashash_match_pairs_epipolar(
+            self.h, C.byref(st), self._arrays(codes), self._arrays(keys), self._arrays(kp), len(pairs),
+            pairs.ctypes.data if len(pairs) else None, F.ctypes.data if len(F) else None, float(max_px),
+            *[(_dptr(a) if self.mem == "device" else (a.ctypes.data if a.size else None)) for a in o],
+            C.byref(stats)))
+        return o, stats.as_dict()
+
+
+def codes_to_numpy(codes):
+    """Device int64 [n,2] code tensors -> numpy uint64."""
+    return [c.cpu().numpy().view(np.uint64) for c in codes]

@@ -1,0 +1,1054 @@
+// Host runtime and C ABI of the CasHash matcher (see include/cashash.h).
+//
+// Device-memory mode runs every step on caller buffers already in HBM.
+// Host-memory mode streams images to the device under a byte budget: blocks
+// of images are resident at a time and block pairs are visited in the load
+// order of the paper's matching scheduler ("Data Scheduling Strategy for
+// Image Matching"), with the next block prefetched on a copy stream.
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cashash.h"
+#include "cashash_internal.h"
+#include "cashash_launch.h"
+#include "cashash_sched.h"
+
+using namespace cashash;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess)                                                                       \
+            return fail(e_ == hipErrorOutOfMemory ? CASHASH_E_NOMEM : CASHASH_E_DEVICE, "%s: %s (%s:%d)", \
+                        #x, hipGetErrorString(e_), __FILE__, __LINE__);                           \
+    } while (0)
+
+#define RETCHK(x)            \
+    do {                     \
+        int r_ = (x);        \
+        if (r_ != CASHASH_OK) return r_; \
+    } while (0)
+
+// ------------------------------------------------------------------ buffers
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n) {
+        if (n <= cap && p) return CASHASH_OK;
+        if (p) {
+            hipDeviceSynchronize();  // kernels in flight may still read the old block
+            hipFree(p);
+        }
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(n, 256);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return fail(CASHASH_E_NOMEM, "device allocation of %zu bytes failed", want);
+        }
+        cap = want;
+        return CASHASH_OK;
+    }
+    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct HostPinned {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n) {
+        if (n <= cap && p) return CASHASH_OK;
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(n, 4096);
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return fail(CASHASH_E_NOMEM, "pinned host allocation of %zu bytes failed", want);
+        }
+        cap = want;
+        return CASHASH_OK;
+    }
+    void release() {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Small host vectors are staged into one pinned block and uploaded with a
+// single copy; each piece is 256-byte aligned on the device.
+struct Uploader {
+    std::vector<uint8_t> host;
+    std::vector<size_t> offs;
+    template <class T> size_t add(const std::vector<T>& v) {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+        offs.push_back(off);
+        return off;
+    }
+};
+
+struct cashash_ctx {
+    int device = 0;
+    cashash_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t copy_stream = nullptr;
+    int n_cu = 256;
+    std::vector<double> R64;  // [176][128]
+    DevBuf dR64, dR32, dFrag, dBias, dS, dCount;
+    DevBuf meta[2];           // uploaded tables (images, pairs, items, tiles ...), double-buffered
+    HostPinned meta_host[2];
+    hipEvent_t meta_ev[2] = {nullptr, nullptr};
+    int meta_turn = 0;
+    DevBuf near, tables;      // near-margin masks; bucket tables
+    DevBuf stage, outbuf;     // host-memory mode: resident image slots; per-step outputs
+    HostPinned pin[2];        // host-memory mode upload staging
+    hipEvent_t pin_ev[2] = {nullptr, nullptr};
+    int pin_turn = 0;
+    HostPinned pin_out, pin_small;
+    hipEvent_t slot_load_ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t slot_free_ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+    int64_t last_launches = 0;
+};
+
+static int validate_config(const cashash_config* c) {
+    if (c->k < 1 || c->k > CASHASH_MAX_K) return fail(CASHASH_E_LIMIT, "k=%d outside 1..%d", c->k, CASHASH_MAX_K);
+    if (c->ratio_num <= 0 || c->ratio_den <= 0 || c->ratio_num > 65535 || c->ratio_den > 65535)
+        return fail(CASHASH_E_INVAL, "ratio %d/%d: both must be in 1..65535", c->ratio_num, c->ratio_den);
+    if (c->max_hamming < 0 || c->max_hamming > 128)
+        return fail(CASHASH_E_LIMIT, "max_hamming=%d outside 0..128", c->max_hamming);
+    if (!(c->margin_coef > 0.0) || !std::isfinite(c->margin_coef) || c->margin_coef > 1e3)
+        return fail(CASHASH_E_INVAL, "margin_coef must be positive and finite");
+    if (c->mode != CASHASH_MODE_BATCHED_BF16X2 && c->mode != CASHASH_MODE_PLAIN_FP32_PER_PAIR)
+        return fail(CASHASH_E_INVAL, "unknown mode %d", c->mode);
+    if (c->mem != CASHASH_MEM_HOST && c->mem != CASHASH_MEM_DEVICE)
+        return fail(CASHASH_E_INVAL, "unknown mem %d", c->mem);
+    if (c->device_budget_bytes < 0) return fail(CASHASH_E_INVAL, "negative device budget");
+    return CASHASH_OK;
+}
+
+// The fast projection's rounding error is below 4.6e-5 |r| |x| (bf16 hi+lo
+// representation 2^-16 |r||x| plus fp32 accumulation of 256 exact products
+// even with round-toward-zero, 2^-23 * 256 |r||x|), so it is trusted outside
+// margin_coef |x| only when 5e-5 |r| < margin_coef.
+static int check_rows(const std::vector<double>& R, double coef) {
+    for (int j = 0; j < kRows; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < kDim; ++i) {
+            const double v = R[j * kDim + i];
+            if (!std::isfinite(v)) return fail(CASHASH_E_UNSAFE_MATRIX, "row %d has a non-finite entry", j);
+            s += v * v;
+        }
+        if (!(5e-5 * std::sqrt(s) < coef))
+            return fail(CASHASH_E_UNSAFE_MATRIX, "row %d has norm %.4g: 5e-5*norm must be < margin_coef=%.4g", j,
+                        std::sqrt(s), coef);
+    }
+    return CASHASH_OK;
+}
+
+static uint16_t bf16_round(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;  // round to nearest even (values are finite)
+    return (uint16_t)(u >> 16);
+}
+static double bf16_value(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+// hi = bf16(r) and lo = bf16(r - hi) (r - hi is exact in binary64), laid out
+// as the MFMA A-operand fragments lane l loads for (part, row tile, k step).
+static std::vector<uint16_t> make_frag(const std::vector<double>& R) {
+    std::vector<uint16_t> f((size_t)kFragBytes / 2);
+    for (int rt = 0; rt < kRowTiles; ++rt)
+        for (int ks = 0; ks < 4; ++ks)
+            for (int l = 0; l < 64; ++l)
+                for (int i = 0; i < 8; ++i) {
+                    const double r = R[(16 * rt + l % 16) * kDim + 32 * ks + 8 * (l / 16) + i];
+                    // round binary64 -> bf16 through fp32: exact for the hi part's
+                    // purpose since any rounding error is absorbed by lo
+                    const uint16_t hi = bf16_round((float)r);
+                    const uint16_t lo = bf16_round((float)(r - bf16_value(hi)));
+                    f[((((size_t)0 * kRowTiles + rt) * 4 + ks) * 64 + l) * 8 + i] = hi;
+                    f[((((size_t)1 * kRowTiles + rt) * 4 + ks) * 64 + l) * 8 + i] = lo;
+                }
+    return f;
+}
+
+extern "C" void cashash_default_config(cashash_config* c) {
+    if (!c) return;
+    c->k = 10;
+    c->ratio_num = 4;
+    c->ratio_den = 5;
+    c->max_hamming = 128;
+    c->margin_coef = 1e-3;
+    c->mode = CASHASH_MODE_BATCHED_BF16X2;
+    c->mem = CASHASH_MEM_DEVICE;
+    c->device_budget_bytes = 0;
+    c->stream = nullptr;
+}
+
+extern "C" const char* cashash_last_error(void) { return g_err.c_str(); }
+
+static void destroy_ctx(cashash_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->copy_stream) {
+        hipStreamSynchronize(c->copy_stream);
+        hipStreamDestroy(c->copy_stream);
+    }
+    for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0], &c->meta[1],
+                      &c->near, &c->tables, &c->stage, &c->outbuf})
+        b->release();
+    for (HostPinned* h : {&c->meta_host[0], &c->meta_host[1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
+        h->release();
+    for (hipEvent_t e : {c->ev0, c->ev1, c->meta_ev[0], c->meta_ev[1], c->pin_ev[0], c->pin_ev[1],
+                         c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
+                         c->slot_free_ev[1], c->slot_free_ev[2]})
+        if (e) hipEventDestroy(e);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+extern "C" void cashash_destroy(cashash_ctx* c) { destroy_ctx(c); }
+
+extern "C" int cashash_set_config(cashash_ctx* c, const cashash_config* cfg) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    cashash_config n;
+    if (cfg)
+        n = *cfg;
+    else
+        cashash_default_config(&n);
+    RETCHK(validate_config(&n));
+    RETCHK(check_rows(c->R64, n.margin_coef));
+    if (n.stream != c->cfg.stream || !c->stream) {
+        if (c->stream) hipStreamSynchronize(c->stream);
+        if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+        c->stream = nullptr;
+        c->own_stream = false;
+        if (n.stream) {
+            c->stream = (hipStream_t)n.stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+    }
+    c->cfg = n;
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const double* r_bucket,
+                              const cashash_config* cfg) {
+    if (!out || !r_code || !r_bucket) return fail(CASHASH_E_INVAL, "null argument to cashash_create");
+    *out = nullptr;
+    cashash_config n;
+    if (cfg)
+        n = *cfg;
+    else
+        cashash_default_config(&n);
+    RETCHK(validate_config(&n));
+    std::vector<double> R((size_t)kRows * kDim);
+    std::memcpy(R.data(), r_code, sizeof(double) * kCodeBits * kDim);
+    std::memcpy(R.data() + (size_t)kCodeBits * kDim, r_bucket, sizeof(double) * kTables * kKeyBits * kDim);
+    RETCHK(check_rows(R, n.margin_coef));
+    cashash_ctx* c = new cashash_ctx();
+    c->R64 = std::move(R);
+    auto bail = [&](int code) {
+        std::string keep = g_err;
+        destroy_ctx(c);
+        g_err = keep;
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(CASHASH_E_DEVICE, "no HIP device"));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess)
+        return bail(fail(CASHASH_E_DEVICE, "hipGetDeviceProperties failed"));
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    int r = cashash_set_config(c, &n);
+    if (r) return bail(r);
+    if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+        return bail(fail(CASHASH_E_DEVICE, "stream/event creation failed"));
+    for (hipEvent_t* e : {&c->meta_ev[0], &c->meta_ev[1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
+                          &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
+                          &c->slot_free_ev[2]})
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
+    if ((r = c->pin_small.ensure(4096))) return bail(r);
+    std::vector<float> R32(c->R64.size());
+    for (size_t i = 0; i < R32.size(); ++i) R32[i] = (float)c->R64[i];
+    std::vector<uint16_t> frag = make_frag(c->R64);
+    if ((r = c->dR64.ensure(c->R64.size() * 8)) || (r = c->dR32.ensure(R32.size() * 4)) ||
+        (r = c->dFrag.ensure(frag.size() * 2)) || (r = c->dBias.ensure(kRows * 4)) || (r = c->dS.ensure(kDim * 8)) ||
+        (r = c->dCount.ensure(64 * 8)))
+        return bail(r);
+    if (hipMemcpy(c->dR64.p, c->R64.data(), c->R64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->dR32.p, R32.data(), R32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->dFrag.p, frag.data(), frag.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(CASHASH_E_DEVICE, "upload of projection matrices failed"));
+    *out = c;
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_last_kernel_ms(cashash_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return fail(CASHASH_E_INVAL, "null argument");
+    *ms = c->last_ms;
+    *launches = c->last_launches;
+    return CASHASH_OK;
+}
+
+// ------------------------------------------------------------------ helpers
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Uploads small tables on the compute stream (so they follow the kernels that
+// read the previous contents).  Two buffers alternate; a buffer's pinned
+// source is rewritten only after its previous copy has completed.
+static int upload_meta(cashash_ctx* c, Uploader& up, std::vector<const void*>& dptr) {
+    const int b = c->meta_turn;
+    c->meta_turn ^= 1;
+    HIPCHK(hipEventSynchronize(c->meta_ev[b]));
+    RETCHK(c->meta[b].ensure(up.host.size()));
+    RETCHK(c->meta_host[b].ensure(up.host.size()));
+    std::memcpy(c->meta_host[b].p, up.host.data(), up.host.size());
+    HIPCHK(hipMemcpyAsync(c->meta[b].p, c->meta_host[b].p, up.host.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->meta_ev[b], c->stream));
+    dptr.clear();
+    for (size_t o : up.offs) dptr.push_back(c->meta[b].as<uint8_t>() + o);
+    return CASHASH_OK;
+}
+
+static int check_images(const cashash_images* im) {
+    if (!im || im->n_images < 0 || (im->n_images > 0 && (!im->desc || !im->n_feat)))
+        return fail(CASHASH_E_INVAL, "invalid image set");
+    for (int m = 0; m < im->n_images; ++m) {
+        const int n = im->n_feat[m];
+        if (n < 0) return fail(CASHASH_E_INVAL, "image %d: negative n_feat", m);
+        if (n > CASHASH_MAX_FEAT) return fail(CASHASH_E_LIMIT, "image %d: n_feat=%d > %d", m, n, CASHASH_MAX_FEAT);
+    }
+    return CASHASH_OK;
+}
+
+static bool misaligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) != 0; }
+
+// ------------------------------------------------------------------ codes (device-resident core)
+struct CodeJob {
+    std::vector<ImgDev> imgs;
+    std::vector<CodeOut> outs;
+};
+
+// Column sums over `imgs`, accumulated into c->dS (not cleared here).
+static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
+    std::vector<RowChunk> chunks;
+    for (int m = 0; m < (int)imgs.size(); ++m)
+        for (int r0 = 0; r0 < imgs[m].n; r0 += 2048) chunks.push_back({m, r0, std::min(2048, imgs[m].n - r0), 0});
+    if (chunks.empty()) return CASHASH_OK;
+    Uploader up;
+    up.add(imgs);
+    up.add(chunks);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d));
+    HIPCHK(launch_colsum(c->stream, (const ImgDev*)d[0], (const RowChunk*)d[1], (int)chunks.size(),
+                         c->dS.as<unsigned long long>()));
+    return CASHASH_OK;
+}
+
+// Projection + binary64 fix-up of `imgs` into `outs`, given c->dBias and c->dS.
+static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vector<CodeOut> outs, double n_tot) {
+    std::vector<RowChunk> tiles;
+    int64_t flat = 0;
+    for (int m = 0; m < (int)imgs.size(); ++m) {
+        outs[m].flat = flat;
+        flat += imgs[m].n;
+        for (int r0 = 0; r0 < imgs[m].n; r0 += 16) tiles.push_back({m, r0, std::min(16, imgs[m].n - r0), 0});
+    }
+    if (tiles.empty()) return CASHASH_OK;
+    RETCHK(c->near.ensure((size_t)flat * 24));
+    Uploader up;
+    up.add(imgs);
+    up.add(outs);
+    up.add(tiles);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d));
+    const ImgDev* dI = (const ImgDev*)d[0];
+    const CodeOut* dO = (const CodeOut*)d[1];
+    const RowChunk* dT = (const RowChunk*)d[2];
+    const int nt = (int)tiles.size();
+    const float coef = (float)c->cfg.margin_coef;
+    if (c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2) {
+        const int grid = std::max(1, std::min((nt + 3) / 4, c->n_cu * 8));
+        HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
+                                c->near.as<uint64_t>()));
+    } else {
+        HIPCHK(launch_proj_fp32(c->stream, dI, dO, dT, nt, c->dR32.as<float>(), c->dBias.as<float>(), coef,
+                                c->near.as<uint64_t>()));
+    }
+    HIPCHK(launch_fixup(c->stream, dI, dO, dT, nt, c->near.as<uint64_t>(), c->dR64.as<double>(),
+                        c->dS.as<unsigned long long>(), n_tot, c->dCount.as<unsigned long long>()));
+    return CASHASH_OK;
+}
+
+static int build_codes_device(cashash_ctx* c, const cashash_images* im, uint64_t* const* codes_out,
+                              uint8_t* const* keys_out, int64_t* near_count) {
+    std::vector<ImgDev> imgs(im->n_images);
+    std::vector<CodeOut> outs(im->n_images);
+    double n_tot = 0;
+    for (int m = 0; m < im->n_images; ++m) {
+        const int n = im->n_feat[m];
+        if (n > 0 && (!im->desc[m] || !codes_out[m] || !keys_out[m]))
+            return fail(CASHASH_E_INVAL, "image %d: null descriptor or output pointer", m);
+        if (n > 0 && (misaligned(im->desc[m], 16) || misaligned(codes_out[m], 8) || misaligned(keys_out[m], 2)))
+            return fail(CASHASH_E_INVAL, "image %d: descriptors need 16-byte, codes 8-byte, keys 2-byte alignment", m);
+        imgs[m] = ImgDev{im->desc[m], nullptr, nullptr, nullptr, nullptr, nullptr, n, 0};
+        outs[m] = CodeOut{codes_out[m], keys_out[m], 0};
+        n_tot += n;
+    }
+    if (n_tot == 0) {
+        *near_count = 0;
+        return CASHASH_OK;
+    }
+    HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
+    HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
+    RETCHK(run_colsum(c, imgs));
+    HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot, c->dBias.as<float>()));
+    RETCHK(run_project(c, imgs, outs, n_tot));
+    unsigned long long cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, c->dCount.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *near_count = (int64_t)cnt;
+    return CASHASH_OK;
+}
+
+// ------------------------------------------------------------------ matching (device-resident core)
+struct MatchJob {
+    bool epi = false;
+    double max_px = 0.0;
+    std::vector<ImgDev> imgs;      // all images (train ones get tables)
+    std::vector<int32_t> pair_q, pair_t;
+    std::vector<int64_t> pair_out; // first output slot of each pair
+    const double* F = nullptr;     // host [n_pairs][9]
+    int32_t* o_idx = nullptr;      // device outputs
+    int32_t* o_d1 = nullptr;
+    int32_t* o_d2 = nullptr;
+    int64_t bucket_entries = 0, union_size = 0;
+};
+
+static constexpr int kQueriesPerItem = 32;
+
+// Enqueues bucket tables and matcher launches for J on c->stream, plus the
+// read-back of the statistics into pinned memory; finish_match waits.
+static int launch_match_job(cashash_ctx* c, MatchJob& J) {
+    const int n_img = (int)J.imgs.size();
+    const int64_t n_pairs = (int64_t)J.pair_q.size();
+    // bucket tables for every train image
+    std::vector<int32_t> train_list;
+    std::vector<char> is_train(n_img, 0);
+    for (int64_t p = 0; p < n_pairs; ++p)
+        if (!is_train[J.pair_t[p]]) {
+            is_train[J.pair_t[p]] = 1;
+            train_list.push_back(J.pair_t[p]);
+        }
+    const size_t ent_bytes = J.epi ? sizeof(EntEpi) : sizeof(EntPlain);
+    size_t tbytes = 0;
+    std::vector<size_t> toff(n_img, 0), eoff(n_img, 0);
+    for (int m : train_list) {
+        toff[m] = tbytes;
+        tbytes += (size_t)kTables * kOffStride * 4;
+        tbytes = (tbytes + 255) & ~size_t(255);
+        eoff[m] = tbytes;
+        tbytes += (size_t)kTables * J.imgs[m].n * ent_bytes;
+        tbytes = (tbytes + 255) & ~size_t(255);
+    }
+    RETCHK(c->tables.ensure(tbytes));
+    std::vector<TableOut> touts(n_img, TableOut{nullptr, nullptr});
+    for (int m : train_list) {
+        touts[m] = TableOut{reinterpret_cast<uint32_t*>(c->tables.as<uint8_t>() + toff[m]),
+                            c->tables.as<uint8_t>() + eoff[m]};
+        J.imgs[m].off = touts[m].off;
+        J.imgs[m].ent = touts[m].ent;
+    }
+    // pairs and work items; batched mode orders items by train image so the
+    // waves that run together share one train image's tables in L2
+    std::vector<PairDev> pd(n_pairs);
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        pd[p].qi = J.pair_q[p];
+        pd[p].ti = J.pair_t[p];
+        pd[p].out = J.pair_out[p];
+        for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
+    }
+    std::vector<int64_t> order(n_pairs);
+    std::iota(order.begin(), order.end(), 0);
+    const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
+    if (batched)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return J.pair_t[a] < J.pair_t[b]; });
+    std::vector<Item> items;
+    std::vector<int64_t> item_begin(n_pairs + 1, 0);
+    for (int64_t oi = 0; oi < n_pairs; ++oi) {
+        const int64_t p = order[oi];
+        item_begin[oi] = (int64_t)items.size();
+        const int nq = J.imgs[J.pair_q[p]].n;
+        for (int q0 = 0; q0 < nq; q0 += kQueriesPerItem)
+            items.push_back(Item{(int32_t)p, q0, std::min(kQueriesPerItem, nq - q0), 0});
+    }
+    item_begin[n_pairs] = (int64_t)items.size();
+    if (items.size() > (size_t)INT32_MAX) return fail(CASHASH_E_LIMIT, "too many query tiles in one call");
+    Uploader up;
+    up.add(J.imgs);
+    up.add(touts);
+    up.add(train_list);
+    up.add(pd);
+    up.add(items);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d));
+    const ImgDev* dI = (const ImgDev*)d[0];
+    const TableOut* dTo = (const TableOut*)d[1];
+    const int32_t* dTrain = (const int32_t*)d[2];
+    const PairDev* dP = (const PairDev*)d[3];
+    const Item* dItems = (const Item*)d[4];
+    MatchParams prm;
+    prm.k = c->cfg.k;
+    prm.tau = c->cfg.max_hamming;
+    prm.num2 = (int64_t)c->cfg.ratio_num * c->cfg.ratio_num;
+    prm.den2 = (int64_t)c->cfg.ratio_den * c->cfg.ratio_den;
+    prm.max_px = J.max_px;
+    unsigned long long* stats = c->dCount.as<unsigned long long>() + 8;
+    uint32_t* counter = reinterpret_cast<uint32_t*>(c->dCount.as<unsigned long long>() + 16);
+    HIPCHK(launch_fill_u64(c->stream, stats, 2, 0ull));
+    if (batched) {
+        HIPCHK(launch_bucket(c->stream, J.epi, dI, dTo, dTrain, (int)train_list.size()));
+        HIPCHK(launch_fill_u32(c->stream, counter, 1, 0u));
+        const int blocks_needed = (int)((items.size() + kWavesPerBlock - 1) / kWavesPerBlock);
+        const int grid = std::max(1, std::min(blocks_needed, c->n_cu * 7));
+        HIPCHK(hipEventRecord(c->ev0, c->stream));
+        HIPCHK(launch_match(c->stream, J.epi, grid, dI, dP, dItems, (int32_t)items.size(), counter, prm, J.o_idx,
+                            J.o_d1, J.o_d2, stats));
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        c->last_launches += 1;
+    } else {
+        // plain form: per pair, the train image's tables (first use) and one
+        // matcher launch over that pair's query tiles
+        std::vector<char> built(n_img, 0);
+        HIPCHK(hipEventRecord(c->ev0, c->stream));
+        for (int64_t oi = 0; oi < n_pairs; ++oi) {
+            const int64_t p = order[oi];
+            const int t = J.pair_t[p];
+            if (!built[t]) {
+                built[t] = 1;
+                const int slot = (int)(std::find(train_list.begin(), train_list.end(), t) - train_list.begin());
+                HIPCHK(launch_bucket(c->stream, J.epi, dI, dTo, dTrain + slot, 1));
+            }
+            const int64_t nit = item_begin[oi + 1] - item_begin[oi];
+            if (nit == 0) continue;
+            HIPCHK(launch_match(c->stream, J.epi, (int)((nit + kWavesPerBlock - 1) / kWavesPerBlock), dI, dP,
+                                dItems + item_begin[oi], (int32_t)nit, nullptr, prm, J.o_idx, J.o_d1, J.o_d2, stats));
+        }
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        c->last_launches += n_pairs;
+    }
+    HIPCHK(hipMemcpyAsync(c->pin_small.p, stats, 16, hipMemcpyDeviceToHost, c->stream));
+    return CASHASH_OK;
+}
+
+static int finish_match_job(cashash_ctx* c, MatchJob& J) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const unsigned long long* st = reinterpret_cast<const unsigned long long*>(c->pin_small.p);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms += ms;
+    J.bucket_entries += (int64_t)st[0];
+    J.union_size += (int64_t)st[1];
+    return CASHASH_OK;
+}
+
+// ------------------------------------------------------------------ host-memory mode
+static size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Chunked upload of caller host memory through two pinned buffers on the copy
+// stream: the CPU fills one buffer while the other is in flight.
+static int h2d_staged(cashash_ctx* c, void* dst, const void* src, size_t bytes, int64_t* h2d) {
+    const size_t chunk = (size_t)16 << 20;
+    RETCHK(c->pin[0].ensure(chunk));
+    RETCHK(c->pin[1].ensure(chunk));
+    for (size_t off = 0; off < bytes; off += chunk) {
+        const int b = c->pin_turn;
+        c->pin_turn ^= 1;
+        HIPCHK(hipEventSynchronize(c->pin_ev[b]));
+        const size_t n = std::min(chunk, bytes - off);
+        std::memcpy(c->pin[b].p, static_cast<const uint8_t*>(src) + off, n);
+        HIPCHK(hipMemcpyAsync(static_cast<uint8_t*>(dst) + off, c->pin[b].p, n, hipMemcpyHostToDevice,
+                              c->copy_stream));
+        HIPCHK(hipEventRecord(c->pin_ev[b], c->copy_stream));
+    }
+    if (h2d) *h2d += (int64_t)bytes;
+    return CASHASH_OK;
+}
+
+static int64_t default_budget(cashash_ctx* c) {
+    if (c->cfg.device_budget_bytes > 0) return c->cfg.device_budget_bytes;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return (int64_t)1 << 30;
+    return (int64_t)(fr / 4);
+}
+
+// Resident layout of one image inside a slot.
+struct SlotImage {
+    size_t desc, codes, keys, kp, end;
+};
+static SlotImage slot_layout(int n, bool with_codes, bool with_kp) {
+    SlotImage L;
+    L.desc = 0;
+    L.codes = al256((size_t)n * kDim);
+    L.keys = L.codes + (with_codes ? al256((size_t)n * 16) : 0);
+    L.kp = L.keys + (with_codes ? al256((size_t)n * 6) : 0);
+    L.end = L.kp + (with_kp ? al256((size_t)n * 8) : 0);
+    return L;
+}
+
+// Codes: pass 1 streams every block for the column sums, pass 2 streams the
+// blocks again (last block first, so the one still resident is reused) to
+// project them.  Two slots: one in use, one being filled.
+static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* const* codes_out,
+                            uint8_t* const* keys_out, int64_t* near_count, cashash_stats* stats) {
+    const int M = im->n_images;
+    double n_tot = 0;
+    std::vector<int64_t> bytes(M);
+    for (int m = 0; m < M; ++m) {
+        const int n = im->n_feat[m];
+        if (n > 0 && (!im->desc[m] || !codes_out[m] || !keys_out[m]))
+            return fail(CASHASH_E_INVAL, "image %d: null descriptor or output pointer", m);
+        bytes[m] = (int64_t)slot_layout(n, true, false).end;
+        n_tot += n;
+    }
+    *near_count = 0;
+    if (n_tot == 0) return CASHASH_OK;
+    const int64_t budget = default_budget(c);
+    const int64_t slot = budget / 2;
+    // blocks of consecutive images
+    std::vector<int> first{0};
+    int64_t fill = 0;
+    for (int m = 0; m < M; ++m) {
+        if (bytes[m] > slot)
+            return fail(CASHASH_E_NOMEM, "image %d needs %lld device bytes; budget %lld allows %lld per block", m,
+                        (long long)bytes[m], (long long)budget, (long long)slot);
+        if (fill + bytes[m] > slot && fill > 0) {
+            first.push_back(m);
+            fill = 0;
+        }
+        fill += bytes[m];
+    }
+    first.push_back(M);
+    const int nb = (int)first.size() - 1;
+    RETCHK(c->stage.ensure((size_t)slot * 2));
+    int64_t h2d = 0, d2h = 0, loads = 0;
+    int resident[2] = {-1, -1};
+    std::vector<size_t> place(M, 0);
+    auto load = [&](int b, int s) -> int {
+        if (resident[s] == b) return CASHASH_OK;
+        HIPCHK(hipStreamWaitEvent(c->copy_stream, c->slot_free_ev[s], 0));
+        size_t off = (size_t)s * slot;
+        for (int m = first[b]; m < first[b + 1]; ++m) {
+            place[m] = off;
+            if (im->n_feat[m] > 0)
+                RETCHK(h2d_staged(c, c->stage.as<uint8_t>() + off, im->desc[m], (size_t)im->n_feat[m] * kDim, &h2d));
+            off += (size_t)bytes[m];
+            loads++;
+        }
+        HIPCHK(hipEventRecord(c->slot_load_ev[s], c->copy_stream));
+        resident[s] = b;
+        return CASHASH_OK;
+    };
+    auto views = [&](int b, std::vector<ImgDev>& iv, std::vector<CodeOut>& ov) {
+        iv.clear();
+        ov.clear();
+        for (int m = first[b]; m < first[b + 1]; ++m) {
+            const int n = im->n_feat[m];
+            const SlotImage L = slot_layout(n, true, false);
+            uint8_t* base = c->stage.as<uint8_t>() + place[m];
+            iv.push_back(ImgDev{base + L.desc, nullptr, nullptr, nullptr, nullptr, nullptr, n, 0});
+            ov.push_back(CodeOut{reinterpret_cast<uint64_t*>(base + L.codes), base + L.keys, 0});
+        }
+    };
+    HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
+    HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
+    std::vector<ImgDev> iv;
+    std::vector<CodeOut> ov;
+    for (int b = 0; b < nb; ++b) {
+        const int s = b & 1;
+        RETCHK(load(b, s));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
+        views(b, iv, ov);
+        RETCHK(run_colsum(c, iv));
+        HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
+        if (b + 1 < nb) RETCHK(load(b + 1, (b + 1) & 1));  // prefetch while the sums run
+    }
+    HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot, c->dBias.as<float>()));
+    for (int b = nb - 1; b >= 0; --b) {
+        int s = resident[0] == b ? 0 : resident[1] == b ? 1 : (b & 1);
+        RETCHK(load(b, s));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
+        views(b, iv, ov);
+        RETCHK(run_project(c, iv, ov, n_tot));
+        size_t out_bytes = 0;
+        for (int m = first[b]; m < first[b + 1]; ++m) out_bytes += (size_t)im->n_feat[m] * 22;
+        RETCHK(c->pin_out.ensure(out_bytes));
+        size_t po = 0;
+        for (int m = first[b]; m < first[b + 1]; ++m) {
+            const size_t n = (size_t)im->n_feat[m];
+            if (!n) continue;
+            const SlotImage L = slot_layout((int)n, true, false);
+            uint8_t* base = c->stage.as<uint8_t>() + place[m];
+            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out.p + po, base + L.codes, n * 16, hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out.p + po + n * 16, base + L.keys, n * 6,
+                                  hipMemcpyDeviceToHost, c->stream));
+            po += n * 22;
+        }
+        HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        po = 0;
+        for (int m = first[b]; m < first[b + 1]; ++m) {
+            const size_t n = (size_t)im->n_feat[m];
+            if (!n) continue;
+            std::memcpy(codes_out[m], (uint8_t*)c->pin_out.p + po, n * 16);
+            std::memcpy(keys_out[m], (uint8_t*)c->pin_out.p + po + n * 16, n * 6);
+            po += n * 22;
+            d2h += (int64_t)n * 22;
+        }
+    }
+    unsigned long long cnt = 0;
+    HIPCHK(hipMemcpy(&cnt, c->dCount.p, 8, hipMemcpyDeviceToHost));
+    *near_count = (int64_t)cnt;
+    if (stats) {
+        stats->h2d_bytes = h2d;
+        stats->d2h_bytes = d2h;
+        stats->image_loads = loads;
+    }
+    return CASHASH_OK;
+}
+
+// Matching: the block scheduler's steps run one after another; each step's
+// missing blocks are loaded into free slots of three, the next step's new
+// block is prefetched while the current step computes, and each step's
+// outputs come back through pinned memory.
+static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                      const uint8_t* const* keys, const float* const* kp, MatchJob& J, int32_t* o_idx,
+                      int32_t* o_d1, int32_t* o_d2, cashash_stats* stats) {
+    const int M = im->n_images;
+    const int64_t n_pairs = (int64_t)J.pair_q.size();
+    const size_t ent_bytes = J.epi ? sizeof(EntEpi) : sizeof(EntPlain);
+    std::vector<int64_t> bytes(M), data_bytes(M);
+    for (int m = 0; m < M; ++m) {
+        const int n = im->n_feat[m];
+        data_bytes[m] = (int64_t)slot_layout(n, true, J.epi).end;
+        bytes[m] = data_bytes[m] + (int64_t)(al256((size_t)kTables * kOffStride * 4) +
+                                             al256((size_t)kTables * n * ent_bytes));
+    }
+    // three image slots plus bucket tables for up to two blocks
+    const int64_t budget = default_budget(c);
+    const int64_t slot = budget / 5;
+    std::vector<int32_t> pv((size_t)2 * n_pairs);
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        pv[2 * p] = J.pair_q[p];
+        pv[2 * p + 1] = J.pair_t[p];
+    }
+    Schedule S;
+    const int pr = plan_schedule(M, bytes.data(), n_pairs, pv.data(), slot, S);
+    if (pr == -1)
+        return fail(CASHASH_E_NOMEM, "an image does not fit the device budget (%lld bytes per block of %lld)",
+                    (long long)slot, (long long)budget);
+    if (pr) return fail(CASHASH_E_INVAL, "scheduler rejected the pair list");
+    RETCHK(c->stage.ensure((size_t)slot * 3));
+    int slot_block[3] = {-1, -1, -1};
+    int64_t slot_used_at[3] = {-1, -1, -1};
+    std::vector<size_t> place(M, 0);
+    int64_t h2d = 0, d2h = 0, loads = 0;
+    auto load_block = [&](int b, int s) -> int {
+        HIPCHK(hipStreamWaitEvent(c->copy_stream, c->slot_free_ev[s], 0));
+        size_t off = (size_t)s * slot;
+        for (int i = S.block_first[b]; i < S.block_first[b + 1]; ++i) {
+            const int m = S.block_images[i];
+            const size_t n = (size_t)im->n_feat[m];
+            const SlotImage L = slot_layout((int)n, true, J.epi);
+            uint8_t* base = c->stage.as<uint8_t>() + off;
+            place[m] = off;
+            if (n) {
+                RETCHK(h2d_staged(c, base + L.desc, im->desc[m], n * kDim, &h2d));
+                RETCHK(h2d_staged(c, base + L.codes, codes[m], n * 16, &h2d));
+                RETCHK(h2d_staged(c, base + L.keys, keys[m], n * 6, &h2d));
+                if (J.epi) RETCHK(h2d_staged(c, base + L.kp, kp[m], n * 8, &h2d));
+            }
+            off += (size_t)data_bytes[m];
+            loads++;
+        }
+        HIPCHK(hipEventRecord(c->slot_load_ev[s], c->copy_stream));
+        slot_block[s] = b;
+        return CASHASH_OK;
+    };
+    // a slot for block b that holds neither of the protected blocks, least recently used first
+    auto pick_slot = [&](int p0, int p1) {
+        int best = -1;
+        for (int s = 0; s < 3; ++s) {
+            if (slot_block[s] == p0 || slot_block[s] == p1) continue;
+            if (best < 0 || slot_used_at[s] < slot_used_at[best]) best = s;
+        }
+        return best;
+    };
+    auto slot_of = [&](int b) {
+        for (int s = 0; s < 3; ++s)
+            if (slot_block[s] == b) return s;
+        return -1;
+    };
+    c->last_ms = 0.0;
+    for (size_t st = 0; st < S.steps.size(); ++st) {
+        const SchedStep& step = S.steps[st];
+        for (int b : {step.bi, step.bk}) {
+            if (slot_of(b) >= 0) continue;
+            const int s = pick_slot(step.bi, step.bk);
+            RETCHK(load_block(b, s));
+        }
+        const int si = slot_of(step.bi), sk = slot_of(step.bk);
+        HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[si], 0));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[sk], 0));
+        slot_used_at[si] = slot_used_at[sk] = (int64_t)st;
+        MatchJob Js;
+        Js.epi = J.epi;
+        Js.max_px = J.max_px;
+        Js.imgs.assign(M, ImgDev{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0});
+        for (int b : {step.bi, step.bk})
+            for (int i = S.block_first[b]; i < S.block_first[b + 1]; ++i) {
+                const int m = S.block_images[i];
+                const int n = im->n_feat[m];
+                const SlotImage L = slot_layout(n, true, J.epi);
+                uint8_t* base = c->stage.as<uint8_t>() + place[m];
+                Js.imgs[m] = ImgDev{base + L.desc, reinterpret_cast<const uint64_t*>(base + L.codes), base + L.keys,
+                                    J.epi ? reinterpret_cast<const float*>(base + L.kp) : nullptr, nullptr, nullptr,
+                                    n, 0};
+            }
+        std::vector<double> Fs;
+        int64_t nq = 0;
+        for (int64_t i = step.pair_begin; i < step.pair_end; ++i) {
+            const int64_t p = S.order[i];
+            Js.pair_q.push_back(J.pair_q[p]);
+            Js.pair_t.push_back(J.pair_t[p]);
+            Js.pair_out.push_back(nq);
+            nq += im->n_feat[J.pair_q[p]];
+            if (J.epi) Fs.insert(Fs.end(), J.F + 9 * p, J.F + 9 * p + 9);
+        }
+        Js.F = J.epi ? Fs.data() : nullptr;
+        RETCHK(c->outbuf.ensure((size_t)std::max<int64_t>(nq, 1) * 12));
+        Js.o_idx = c->outbuf.as<int32_t>();
+        Js.o_d1 = Js.o_idx + nq;
+        Js.o_d2 = Js.o_d1 + nq;
+        RETCHK(launch_match_job(c, Js));
+        HIPCHK(hipEventRecord(c->slot_free_ev[si], c->stream));
+        HIPCHK(hipEventRecord(c->slot_free_ev[sk], c->stream));
+        RETCHK(c->pin_out.ensure((size_t)std::max<int64_t>(nq, 1) * 12));
+        if (nq) HIPCHK(hipMemcpyAsync(c->pin_out.p, c->outbuf.p, (size_t)nq * 12, hipMemcpyDeviceToHost, c->stream));
+        // prefetch the next step's new block while this one computes
+        if (st + 1 < S.steps.size()) {
+            const SchedStep& nx = S.steps[st + 1];
+            for (int b : {nx.bi, nx.bk}) {
+                if (slot_of(b) >= 0) continue;
+                const int s = pick_slot(step.bi, step.bk);
+                if (s < 0) break;
+                RETCHK(load_block(b, s));
+                break;  // one block ahead
+            }
+        }
+        RETCHK(finish_match_job(c, Js));
+        const int32_t* ho = reinterpret_cast<const int32_t*>(c->pin_out.p);
+        for (size_t i = 0; i < Js.pair_q.size(); ++i) {
+            const int64_t p = S.order[step.pair_begin + (int64_t)i];
+            const int64_t n = im->n_feat[J.pair_q[p]];
+            if (!n) continue;
+            std::memcpy(o_idx + J.pair_out[p], ho + Js.pair_out[i], (size_t)n * 4);
+            std::memcpy(o_d1 + J.pair_out[p], ho + nq + Js.pair_out[i], (size_t)n * 4);
+            std::memcpy(o_d2 + J.pair_out[p], ho + 2 * nq + Js.pair_out[i], (size_t)n * 4);
+        }
+        d2h += nq * 12;
+        J.bucket_entries += Js.bucket_entries;
+        J.union_size += Js.union_size;
+    }
+    if (stats) {
+        stats->h2d_bytes = h2d;
+        stats->d2h_bytes = d2h;
+        stats->image_loads = loads;
+    }
+    return CASHASH_OK;
+}
+
+// Exposed for tests of the host logic: plan the block schedule and report its
+// shape.  steps_out (may be NULL) receives up to max_steps rows of
+// (bi, bk, first pair position, end pair position); order_out (may be NULL)
+// receives the n_pairs pair indices in visiting order.
+extern "C" int cashash_plan_schedule(int32_t n_images, const int64_t* img_bytes, int64_t n_pairs,
+                                     const int32_t* pairs, int64_t slot_bytes, int64_t* n_steps, int64_t* n_blocks,
+                                     int64_t* block_loads, int64_t* image_loads, int64_t* steps_out,
+                                     int64_t max_steps, int64_t* order_out) {
+    if (!img_bytes || (n_pairs > 0 && !pairs) || !n_steps || !n_blocks || !block_loads || !image_loads)
+        return fail(CASHASH_E_INVAL, "null argument");
+    Schedule S;
+    const int r = plan_schedule(n_images, img_bytes, n_pairs, pairs, slot_bytes, S);
+    if (r == -1) return fail(CASHASH_E_NOMEM, "an image exceeds the slot size");
+    if (r) return fail(CASHASH_E_INVAL, "bad schedule input");
+    *n_steps = (int64_t)S.steps.size();
+    *n_blocks = (int64_t)S.block_first.size() - 1;
+    *block_loads = S.block_loads;
+    *image_loads = S.image_loads;
+    if (steps_out)
+        for (int64_t i = 0; i < std::min<int64_t>(max_steps, (int64_t)S.steps.size()); ++i) {
+            steps_out[4 * i] = S.steps[i].bi;
+            steps_out[4 * i + 1] = S.steps[i].bk;
+            steps_out[4 * i + 2] = S.steps[i].pair_begin;
+            steps_out[4 * i + 3] = S.steps[i].pair_end;
+        }
+    if (order_out) std::copy(S.order.begin(), S.order.end(), order_out);
+    return CASHASH_OK;
+}
+
+// ------------------------------------------------------------------ public entry points
+static void zero_stats(cashash_stats* s) {
+    if (s) std::memset(s, 0, sizeof *s);
+}
+
+extern "C" int cashash_build_codes(cashash_ctx* c, const cashash_images* im, uint64_t* const* codes_out,
+                                   uint8_t* const* keys_out, cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(check_images(im));
+    if (im->n_images > 0 && (!codes_out || !keys_out)) return fail(CASHASH_E_INVAL, "null output arrays");
+    zero_stats(stats);
+    const double t0 = now_ms();
+    int64_t near_count = 0;
+    if (c->cfg.mem == CASHASH_MEM_DEVICE) {
+        RETCHK(build_codes_device(c, im, codes_out, keys_out, &near_count));
+    } else {
+        RETCHK(build_codes_host(c, im, codes_out, keys_out, &near_count, stats));
+    }
+    if (stats) {
+        stats->near_margin_recomputes = near_count;
+        stats->ms_codes = now_ms() - t0;
+    }
+    return CASHASH_OK;
+}
+
+static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                        const uint8_t* const* keys, const float* const* kp, int64_t n_pairs, const int32_t* pairs,
+                        const double* F, double max_px, bool epi, int32_t* o_idx, int32_t* o_d1, int32_t* o_d2,
+                        cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(check_images(im));
+    if (n_pairs < 0) return fail(CASHASH_E_INVAL, "negative n_pairs");
+    zero_stats(stats);
+    if (n_pairs == 0) return CASHASH_OK;
+    if (!pairs || !codes || !keys) return fail(CASHASH_E_INVAL, "null pairs, codes or keys");
+    if (epi) {
+        if (!kp || !F) return fail(CASHASH_E_INVAL, "null keypoints or F");
+        if (!(max_px >= 0.0) || !std::isfinite(max_px)) return fail(CASHASH_E_INVAL, "max_px must be finite and >= 0");
+        for (int64_t i = 0; i < 9 * n_pairs; ++i)
+            if (!std::isfinite(F[i])) return fail(CASHASH_E_INVAL, "F of pair %lld is not finite", (long long)(i / 9));
+    }
+    const double t0 = now_ms();
+    MatchJob J;
+    J.epi = epi;
+    J.max_px = max_px;
+    J.F = F;
+    J.pair_q.resize(n_pairs);
+    J.pair_t.resize(n_pairs);
+    J.pair_out.resize(n_pairs);
+    int64_t total_q = 0;
+    std::vector<char> used(im->n_images, 0);
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int32_t q = pairs[2 * p], t = pairs[2 * p + 1];
+        if (q < 0 || t < 0 || q >= im->n_images || t >= im->n_images)
+            return fail(CASHASH_E_INVAL, "pair %lld = (%d, %d) out of range", (long long)p, q, t);
+        J.pair_q[p] = q;
+        J.pair_t[p] = t;
+        J.pair_out[p] = total_q;
+        total_q += im->n_feat[q];
+        used[q] = used[t] = 1;
+    }
+    for (int m = 0; m < im->n_images; ++m) {
+        if (!used[m] || im->n_feat[m] == 0) continue;
+        if (!im->desc[m] || !codes[m] || !keys[m] || (epi && !kp[m]))
+            return fail(CASHASH_E_INVAL, "image %d: null descriptor, code, key or keypoint pointer", m);
+        if (misaligned(im->desc[m], 16) || misaligned(codes[m], 8) || misaligned(keys[m], 2) ||
+            (epi && misaligned(kp[m], 4)))
+            return fail(CASHASH_E_INVAL, "image %d: misaligned buffer", m);
+    }
+    if (total_q > 0 && (!o_idx || !o_d1 || !o_d2)) return fail(CASHASH_E_INVAL, "null output arrays");
+    c->last_launches = 0;
+    if (c->cfg.mem == CASHASH_MEM_DEVICE) {
+        if (misaligned(o_idx, 4) || misaligned(o_d1, 4) || misaligned(o_d2, 4))
+            return fail(CASHASH_E_INVAL, "misaligned output arrays");
+        J.imgs.resize(im->n_images);
+        for (int m = 0; m < im->n_images; ++m)
+            J.imgs[m] = ImgDev{im->desc[m], codes[m], keys[m], epi ? kp[m] : nullptr, nullptr, nullptr,
+                               im->n_feat[m], 0};
+        J.o_idx = o_idx;
+        J.o_d1 = o_d1;
+        J.o_d2 = o_d2;
+        c->last_ms = 0.0;
+        RETCHK(launch_match_job(c, J));
+        RETCHK(finish_match_job(c, J));
+    } else {
+        RETCHK(match_host(c, im, codes, keys, kp, J, o_idx, o_d1, o_d2, stats));
+    }
+    if (stats) {
+        stats->pairs = n_pairs;
+        stats->queries = total_q;
+        stats->bucket_entries = J.bucket_entries;
+        stats->union_size = J.union_size;
+        stats->ms_match = now_ms() - t0;
+    }
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_match_pairs(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                                   const uint8_t* const* keys, int64_t n_pairs, const int32_t* pairs,
+                                   int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats) {
+    return match_common(c, im, codes, keys, nullptr, n_pairs, pairs, nullptr, 0.0, false, match_idx, d1sq, d2sq,
+                        stats);
+}
+
+extern "C" int cashash_match_pairs_epipolar(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                                            const uint8_t* const* keys, const float* const* kp_xy, int64_t n_pairs,
+                                            const int32_t* pairs, const double* F, double max_px, int32_t* match_idx,
+                                            int32_t* d1sq, int32_t* d2sq, cashash_stats* stats) {
+    return match_common(c, im, codes, keys, kp_xy, n_pairs, pairs, F, max_px, true, match_idx, d1sq, d2sq, stats);
+}

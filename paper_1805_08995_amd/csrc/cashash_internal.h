@@ -1,0 +1,99 @@
+// Device-side data layouts shared by the host runtime and the kernels of the
+// CasHash matcher (gfx950).  Nothing here is part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cashash {
+
+constexpr int kDim = 128;          // SIFT dimension d
+constexpr int kTables = 6;         // lookup tables (Step 1)
+constexpr int kKeyBits = 8;        // m bits per lookup key
+constexpr int kCodeBits = 128;     // n bits of the remapping code (Step 2)
+constexpr int kRows = kCodeBits + kTables * kKeyBits;  // 176 projection rows
+constexpr int kRowTiles = kRows / 16;                   // 11 MFMA row tiles
+constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
+constexpr int kMaxK = 64;
+constexpr int kListCap = 1024;     // per-wave LDS candidate list (u32 keys)
+constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
+
+// Per-image view.  desc/codes/keys/kp are the caller's (or staged) buffers;
+// off/ent are the bucket tables the library builds for train images.
+struct ImgDev {
+    const uint8_t* desc;   // [n][128]
+    const uint64_t* codes; // [n][2]
+    const uint8_t* keys;   // [n][6]
+    const float* kp;       // [n][2] or null
+    const uint32_t* off;   // [6][257] bucket start offsets, or null
+    const uint8_t* ent;    // [6][n] bucket-ordered entries, or null
+    int32_t n;
+    int32_t pad;
+};
+
+// Writable per-image outputs of the code builder.
+struct CodeOut {
+    uint64_t* codes;   // [n][2]
+    uint8_t* keys;     // [n][6]
+    int64_t flat;      // offset of this image in the flat near-margin mask array
+};
+
+// Writable bucket tables of one train image.
+struct TableOut {
+    uint32_t* off;     // [6][257]
+    uint8_t* ent;      // [6][n] entries of kEntBytes<EPI>
+};
+
+// Bucket-ordered entry of table t: the train point's 128-bit code, its six
+// keys (bytes 0..5 of `kid`) and its index (bits 48..63), plus the keypoint
+// for the epipolar form.  Entries of one bucket are contiguous and in
+// ascending index order.
+struct EntPlain {
+    uint64_t c0, c1, kid;
+};
+struct EntEpi {
+    uint64_t c0, c1, kid;
+    float x, y;
+};
+template <bool EPI> struct EntOf { using T = EntPlain; };
+template <> struct EntOf<true> { using T = EntEpi; };
+
+struct PairDev {
+    int32_t qi, ti;     // query image, train image
+    int64_t out;        // first output slot of this pair
+    double F[9];        // row-major fundamental matrix (epipolar form)
+};
+
+struct Item {           // a tile of consecutive queries of one pair
+    int32_t pair;
+    int32_t q0;
+    int32_t nq;
+    int32_t pad;
+};
+
+struct RowChunk {       // rows [r0, r0 + nr) of image img
+    int32_t img;
+    int32_t r0;
+    int32_t nr;
+    int32_t pad;
+};
+
+struct MatchParams {
+    int32_t k;
+    int32_t tau;
+    int64_t num2;       // ratio_num^2
+    int64_t den2;       // ratio_den^2
+    double max_px;
+};
+
+struct ProjParams {
+    float margin_coef;
+    int32_t n_tiles;
+    double n_tot;       // descriptor count of the set, as binary64
+};
+
+// Bf16 hi/lo fragments of the 176 projection rows, pre-arranged so that lane
+// l of a wave loads its 8 values for (part, row tile, k step) as one 16-byte
+// vector: frag[part][rt][ks][l][i] = part(R[16 rt + l % 16][32 ks + 8 (l / 16) + i]).
+constexpr int kFragBytes = 2 * kRowTiles * 4 * 64 * 16;
+
+}  // namespace cashash

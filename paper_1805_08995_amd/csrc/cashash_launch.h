@@ -1,0 +1,23 @@
+// Host-side launchers of the device kernels (defined in cashash_kernels.hip).
+#pragma once
+#include "cashash_internal.h"
+
+namespace cashash {
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsigned long long v);
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, int64_t n, uint32_t v);
+hipError_t launch_colsum(hipStream_t s, const ImgDev* imgs, const RowChunk* chunks, int n_chunks,
+                         unsigned long long* S);
+hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long* S, double n_tot, float* bias);
+hipError_t launch_proj_mfma(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
+                            int n_tiles, const uint4* frag, const float* bias, float margin, uint64_t* near);
+hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
+                            int n_tiles, const float* R32, const float* bias, float margin, uint64_t* near);
+hipError_t launch_fixup(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles, int n_tiles,
+                        const uint64_t* near, const double* R, const unsigned long long* S, double n_tot,
+                        unsigned long long* counter);
+hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const TableOut* touts,
+                         const int32_t* train_list, int n_train);
+hipError_t launch_match(hipStream_t s, bool epi, int grid, const ImgDev* imgs, const PairDev* pairs, const Item* items,
+                        int32_t n_items, uint32_t* counter, const MatchParams& prm, int32_t* o_idx, int32_t* o_d1,
+                        int32_t* o_d2, unsigned long long* stats);
+}  // namespace cashash
