@@ -82,6 +82,7 @@ typedef struct {
     int64_t pairs, queries;
     int64_t bucket_entries;         /* sum over queries of the six same-key bucket sizes */
     int64_t union_size;             /* sum over queries of the candidate-set size (after the band) */
+    int64_t ranked;                 /* sum over queries of the kept top-k size min(k, candidates) */
     int64_t near_margin_recomputes; /* projections recomputed in binary64 */
     int64_t h2d_bytes, d2h_bytes, image_loads;
     double ms_codes, ms_match;      /* wall time of the call */

@@ -465,7 +465,7 @@ struct MatchJob {
     int32_t* o_idx = nullptr;      // device outputs
     int32_t* o_d1 = nullptr;
     int32_t* o_d2 = nullptr;
-    int64_t bucket_entries = 0, union_size = 0;
+    int64_t bucket_entries = 0, union_size = 0, ranked = 0;
 };
 
 static constexpr int kQueriesPerItem = 32;
@@ -549,7 +549,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     prm.max_px = J.max_px;
     unsigned long long* stats = c->dCount.as<unsigned long long>() + 8;
     uint32_t* counter = reinterpret_cast<uint32_t*>(c->dCount.as<unsigned long long>() + 16);
-    HIPCHK(launch_fill_u64(c->stream, stats, 2, 0ull));
+    HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
     if (batched) {
         HIPCHK(launch_bucket(c->stream, J.epi, dI, dTo, dTrain, (int)train_list.size()));
         HIPCHK(launch_fill_u32(c->stream, counter, 1, 0u));
@@ -581,7 +581,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         HIPCHK(hipEventRecord(c->ev1, c->stream));
         c->last_launches += n_pairs;
     }
-    HIPCHK(hipMemcpyAsync(c->pin_small.p, stats, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(c->pin_small.p, stats, 24, hipMemcpyDeviceToHost, c->stream));
     return CASHASH_OK;
 }
 
@@ -593,6 +593,7 @@ static int finish_match_job(cashash_ctx* c, MatchJob& J) {
     c->last_ms += ms;
     J.bucket_entries += (int64_t)st[0];
     J.union_size += (int64_t)st[1];
+    J.ranked += (int64_t)st[2];
     return CASHASH_OK;
 }
 
@@ -904,6 +905,7 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         d2h += nq * 12;
         J.bucket_entries += Js.bucket_entries;
         J.union_size += Js.union_size;
+        J.ranked += Js.ranked;
     }
     if (stats) {
         stats->h2d_bytes = h2d;
@@ -1034,6 +1036,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
         stats->queries = total_q;
         stats->bucket_entries = J.bucket_entries;
         stats->union_size = J.union_size;
+        stats->ranked = J.ranked;
         stats->ms_match = now_ms() - t0;
     }
     return CASHASH_OK;

@@ -460,7 +460,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     uint32_t* list = s_list[wv];
     uint32_t* sel = s_sel[wv];
     const int part = lane & 3;
-    uint64_t st_bucket = 0;
+    uint64_t st_bucket = 0, st_ranked = 0;
     uint32_t st_union = 0;
     uint64_t st_union64 = 0;
 
@@ -536,6 +536,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
 #define CAND(e) (in_list ? ((e) < n_valid ? list[(e)] : ~0u) : key_at<EPI>((e), ent, n_t, qr, prm.tau, dd, dummy))
 
             const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
+            st_ranked += kk;
             int32_t r_idx = -1, r_d1 = -1, r_d2 = -1;
             if (kk > 0) {
                 // ---- Step 3: threshold of the kk-th key by counting passes
@@ -653,6 +654,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     if (lane == 0 && stats) {
         atomicAdd(&stats[0], (unsigned long long)st_bucket);
         atomicAdd(&stats[1], (unsigned long long)st_union64);
+        atomicAdd(&stats[2], (unsigned long long)st_ranked);
     }
 }
 
