@@ -160,6 +160,8 @@ def main():
                   "bucket_entries_per_query": round(st_match["bucket_entries"] / st_match["queries"], 2),
                   "union_per_query": round(st_match["union_size"] / st_match["queries"], 2),
                   "matches": int((ref[0] >= 0).sum()), "ms_codes": round(st_codes["ms_codes"], 3),
+                  "launch_shape": {"tile_queries": st_match["tile_queries"],
+                                   "blocks_per_cu": st_match["blocks_per_cu"]},
                   "ms_match": round(st_match["ms_match"], 3)},
     }
     if not args.no_plain:
@@ -169,7 +171,8 @@ def main():
         plain_value = n_pairs * max(1, min(args.steps, 2)) / dtp
         same = all(np.array_equal(a, o.cpu().numpy()) for a, o in zip(ref, outs))
         result["plain_fp32_per_pair"] = {"value": round(plain_value, 2), "unit": "pairs/s",
-                                         "matcher_launches_per_step": lp, "outputs_identical": same}
+                                         "matcher_launches_per_step": lp, "outputs_identical": same,
+                                         "kernel_ms_per_step": round(float(np.mean(kmsp)), 3)}
         result["speedup_vs_plain"] = round(value / plain_value, 3)
         mp.close()
     m.close()

@@ -85,6 +85,8 @@ typedef struct {
     int64_t ranked;                 /* sum over queries of the kept top-k size min(k, candidates) */
     int64_t near_margin_recomputes; /* projections recomputed in binary64 */
     int64_t h2d_bytes, d2h_bytes, image_loads;
+    int64_t tile_queries;           /* matcher launch shape used: queries per work item, */
+    int64_t blocks_per_cu;          /*   persistent blocks per compute unit (0 in the plain form) */
     double ms_codes, ms_match;      /* wall time of the call */
 } cashash_stats;
 

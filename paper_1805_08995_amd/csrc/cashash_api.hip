@@ -7,6 +7,8 @@
 // Image Matching"), with the next block prefetched on a copy stream.
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -115,6 +117,12 @@ struct Uploader {
     }
 };
 
+// Matcher launch shape: queries per work item and persistent blocks per CU.
+struct Shape {
+    int qt;
+    int bpc;
+};
+
 struct cashash_ctx {
     int device = 0;
     cashash_config cfg{};
@@ -139,6 +147,11 @@ struct cashash_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
     int64_t last_launches = 0;
+    DevBuf items;             // matcher work items of the current job
+    DevBuf counters;          // per-segment work counters of the persistent matcher
+    std::map<std::string, Shape> tuned;
+    bool tune_loaded = false;
+    int last_shape_qt = 0, last_shape_bpc = 0;
 };
 
 static int validate_config(const cashash_config* c) {
@@ -232,7 +245,7 @@ static void destroy_ctx(cashash_ctx* c) {
         hipStreamDestroy(c->copy_stream);
     }
     for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0], &c->meta[1],
-                      &c->near, &c->tables, &c->stage, &c->outbuf})
+                      &c->near, &c->tables, &c->stage, &c->outbuf, &c->items, &c->counters})
         b->release();
     for (HostPinned* h : {&c->meta_host[0], &c->meta_host[1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
         h->release();
@@ -314,7 +327,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     std::vector<uint16_t> frag = make_frag(c->R64);
     if ((r = c->dR64.ensure(c->R64.size() * 8)) || (r = c->dR32.ensure(R32.size() * 4)) ||
         (r = c->dFrag.ensure(frag.size() * 2)) || (r = c->dBias.ensure(kRows * 4)) || (r = c->dS.ensure(kDim * 8)) ||
-        (r = c->dCount.ensure(64 * 8)))
+        (r = c->dCount.ensure(64 * 8)) || (r = c->counters.ensure(kSegments * kCounterStride * 4)))
         return bail(r);
     if (hipMemcpy(c->dR64.p, c->R64.data(), c->R64.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->dR32.p, R32.data(), R32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -468,10 +481,142 @@ struct MatchJob {
     int64_t bucket_entries = 0, union_size = 0, ranked = 0;
 };
 
-static constexpr int kQueriesPerItem = 32;
+// ------------------------------------------------------------------ launch shape and autotuning
+// A launch shape is the number of queries per work item (one wavefront takes
+// one item at a time) and, for the persistent batched launch, the number of
+// resident blocks per compute unit.  A tile's kept candidates must fit the
+// per-wave tile list: qt * k <= kSelCap.
+
+static std::vector<Shape> shape_candidates(int k, bool batched) {
+    std::vector<Shape> v;
+    const int qmax = std::min(64, kSelCap / k);
+    if (batched) {
+        for (int qt : {16, 32, 64})
+            for (int bpc : {4, 6, 8})
+                if (qt <= qmax || qt == 16) v.push_back(Shape{std::min(qt, qmax), bpc});
+    } else {
+        for (int qt : {1, 2, 4, 8, 16, 32})
+            if (qt <= qmax) v.push_back(Shape{qt, 0});
+    }
+    // drop duplicates from clamping
+    std::vector<Shape> u;
+    for (const Shape& s : v) {
+        bool dup = false;
+        for (const Shape& t : u) dup |= (t.qt == s.qt && t.bpc == s.bpc);
+        if (!dup) u.push_back(s);
+    }
+    return u;
+}
+
+static Shape default_shape(int k, bool batched) {
+    return batched ? Shape{std::min(64, kSelCap / k), 5} : Shape{std::min(4, kSelCap / k), 0};
+}
+
+static bool autotune_enabled() {
+    const char* e = std::getenv("CASHASH_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+// Shapes are cached per (form, epipolar, k, train size class, query size
+// class), in memory and, if CASHASH_AUTOTUNE_CACHE names a file, as JSON lines.
+static std::string tune_key(bool batched, bool epi, int k, double mean_nt, double mean_nq) {
+    char b[128];
+    snprintf(b, sizeof b, "gfx950/%s/%s/k%d/nt%d/nq%d", batched ? "batched" : "plain", epi ? "epi" : "plain", k,
+             (int)std::lround(std::log2(std::max(1.0, mean_nt))), (int)std::lround(std::log2(std::max(1.0, mean_nq))));
+    return b;
+}
+
+static void tune_cache_load(cashash_ctx* c);
+static void tune_cache_store(cashash_ctx* c, const std::string& key, Shape sh);
+
+// Per-pair item tables for one query-tile size, in processing order.
+static std::vector<PairTiles> pair_tiles(const MatchJob& J, const std::vector<int64_t>& order, int qt,
+                                         std::vector<int64_t>* first_of) {
+    std::vector<PairTiles> pt;
+    int64_t items = 0;
+    if (first_of) first_of->assign(order.size() + 1, 0);
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const int64_t p = order[oi];
+        const int nq = J.imgs[J.pair_q[p]].n;
+        if (first_of) (*first_of)[oi] = items;
+        if (nq == 0) continue;
+        pt.push_back(PairTiles{(int32_t)p, (int32_t)items});
+        items += (nq + qt - 1) / qt;
+    }
+    if (first_of) (*first_of)[order.size()] = items;
+    return pt;
+}
+
+struct MatchPlan {
+    const ImgDev* dI = nullptr;
+    const PairDev* dP = nullptr;
+    MatchParams prm{};
+    std::vector<int64_t> order;
+    std::vector<int64_t> item_cost_prefix;  // estimated cost of items [0, i) for the current shape
+};
+
+// Estimated cost of each item (its queries times its train image's size),
+// as a prefix sum in item order.
+static void item_costs(const MatchJob& J, const std::vector<int64_t>& order, int qt, std::vector<int64_t>& pre) {
+    pre.assign(1, 0);
+    for (int64_t p : order) {
+        const int nq = J.imgs[J.pair_q[p]].n;
+        const int64_t nt = std::max(1, J.imgs[J.pair_t[p]].n);
+        for (int q0 = 0; q0 < nq; q0 += qt) pre.push_back(pre.back() + (int64_t)std::min(qt, nq - q0) * nt);
+    }
+}
+
+// Generate the work items of shape qt on the device (into c->items).
+static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int qt, const PairTiles* dPT,
+                      int32_t n_pt, int64_t n_items) {
+    if (n_items > (int64_t)INT32_MAX) return fail(CASHASH_E_LIMIT, "too many query tiles in one call");
+    RETCHK(c->items.ensure((size_t)std::max<int64_t>(n_items, 1) * sizeof(Item)));
+    HIPCHK(launch_make_items(c->stream, dPT, n_pt, P.dP, P.dI, qt, c->items.as<Item>(), (int32_t)n_items));
+    return CASHASH_OK;
+}
+
+// The matcher over items [0, n_items) (batched: one persistent launch) or,
+// in the plain form, one launch per pair over its own items.
+static int enqueue_matcher(cashash_ctx* c, const MatchPlan& P, MatchJob& J, Shape sh, bool batched,
+                           const std::vector<int64_t>& first_of, int64_t n_pairs_run, int64_t n_items,
+                           unsigned long long* stats, int64_t* launches) {
+    uint32_t* counter = c->counters.as<uint32_t>();
+    const Item* items = c->items.as<Item>();
+    if (batched) {
+        HIPCHK(launch_fill_u32(c->stream, counter, kSegments * kCounterStride, 0u));
+        const int blocks_needed = (int)((n_items + kWavesPerBlock - 1) / kWavesPerBlock);
+        const int grid = std::max(1, std::min(blocks_needed, c->n_cu * sh.bpc));
+        MatchParams prm = P.prm;
+        // segments of about equal estimated cost (queries x train size), one per XCD
+        const std::vector<int64_t>& cost = P.item_cost_prefix;
+        const int64_t items_total = (int64_t)cost.size() - 1;
+        const int64_t n_run = std::min<int64_t>(n_items, items_total);
+        for (int x = 0; x <= kSegments; ++x) {
+            const double target = (double)cost[n_run] * x / kSegments;
+            const int64_t pos = std::lower_bound(cost.begin(), cost.begin() + n_run + 1, (int64_t)std::ceil(target)) -
+                                cost.begin();
+            prm.seg[x] = (int32_t)std::min<int64_t>(pos, n_run);
+        }
+        prm.seg[0] = 0;
+        prm.seg[kSegments] = (int32_t)n_run;
+        const int64_t waves = (int64_t)grid * kWavesPerBlock;
+        prm.grab = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, n_run / std::max<int64_t>(1, waves * 64)));
+        HIPCHK(launch_match(c->stream, J.epi, grid, P.dI, P.dP, items, (int32_t)n_run, counter, prm, J.o_idx,
+                            J.o_d1, J.o_d2, stats));        *launches += 1;
+    } else {
+        for (int64_t oi = 0; oi < n_pairs_run; ++oi) {
+            const int64_t nit = first_of[oi + 1] - first_of[oi];
+            if (nit == 0) continue;
+            HIPCHK(launch_match(c->stream, J.epi, (int)((nit + kWavesPerBlock - 1) / kWavesPerBlock), P.dI, P.dP,
+                                items + first_of[oi], (int32_t)nit, nullptr, P.prm, J.o_idx, J.o_d1, J.o_d2, stats));
+            *launches += 1;
+        }
+    }
+    return CASHASH_OK;
+}
 
 // Enqueues bucket tables and matcher launches for J on c->stream, plus the
-// read-back of the statistics into pinned memory; finish_match waits.
+// read-back of the statistics into pinned memory; finish_match_job waits.
 static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     const int n_img = (int)J.imgs.size();
     const int64_t n_pairs = (int64_t)J.pair_q.size();
@@ -483,15 +628,15 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
             is_train[J.pair_t[p]] = 1;
             train_list.push_back(J.pair_t[p]);
         }
-    const size_t ent_bytes = J.epi ? sizeof(EntEpi) : sizeof(EntPlain);
     size_t tbytes = 0;
     std::vector<size_t> toff(n_img, 0), eoff(n_img, 0);
+    double sum_nt = 0, sum_nq = 0;
     for (int m : train_list) {
         toff[m] = tbytes;
         tbytes += (size_t)kTables * kOffStride * 4;
         tbytes = (tbytes + 255) & ~size_t(255);
         eoff[m] = tbytes;
-        tbytes += (size_t)kTables * J.imgs[m].n * ent_bytes;
+        tbytes += ent_bytes(J.imgs[m].n, J.epi);
         tbytes = (tbytes + 255) & ~size_t(255);
     }
     RETCHK(c->tables.ensure(tbytes));
@@ -502,87 +647,134 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         J.imgs[m].off = touts[m].off;
         J.imgs[m].ent = touts[m].ent;
     }
-    // pairs and work items; batched mode orders items by train image so the
-    // waves that run together share one train image's tables in L2
     std::vector<PairDev> pd(n_pairs);
     for (int64_t p = 0; p < n_pairs; ++p) {
         pd[p].qi = J.pair_q[p];
         pd[p].ti = J.pair_t[p];
         pd[p].out = J.pair_out[p];
         for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
+        sum_nt += J.imgs[J.pair_t[p]].n;
+        sum_nq += J.imgs[J.pair_q[p]].n;
     }
-    std::vector<int64_t> order(n_pairs);
-    std::iota(order.begin(), order.end(), 0);
+    MatchPlan P;
+    // batched: items ordered by train image, so the waves running together
+    // share one train image's tables in L2
+    P.order.resize(n_pairs);
+    std::iota(P.order.begin(), P.order.end(), 0);
     const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     if (batched)
-        std::stable_sort(order.begin(), order.end(),
+        std::stable_sort(P.order.begin(), P.order.end(),
                          [&](int64_t a, int64_t b) { return J.pair_t[a] < J.pair_t[b]; });
-    std::vector<Item> items;
-    std::vector<int64_t> item_begin(n_pairs + 1, 0);
-    for (int64_t oi = 0; oi < n_pairs; ++oi) {
-        const int64_t p = order[oi];
-        item_begin[oi] = (int64_t)items.size();
-        const int nq = J.imgs[J.pair_q[p]].n;
-        for (int q0 = 0; q0 < nq; q0 += kQueriesPerItem)
-            items.push_back(Item{(int32_t)p, q0, std::min(kQueriesPerItem, nq - q0), 0});
-    }
-    item_begin[n_pairs] = (int64_t)items.size();
-    if (items.size() > (size_t)INT32_MAX) return fail(CASHASH_E_LIMIT, "too many query tiles in one call");
+    // launch shapes: cached, tuned now, or the default
+    tune_cache_load(c);
+    const std::string key = tune_key(batched, J.epi, c->cfg.k, n_pairs ? sum_nt / n_pairs : 0.0,
+                                     n_pairs ? sum_nq / n_pairs : 0.0);
+    std::vector<Shape> cands;
+    auto hit = c->tuned.find(key);
+    const bool tune = hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
+    if (hit != c->tuned.end())
+        cands.push_back(Shape{std::min(hit->second.qt, kSelCap / c->cfg.k), hit->second.bpc});
+    else if (tune)
+        cands = shape_candidates(c->cfg.k, batched);
+    else
+        cands.push_back(default_shape(c->cfg.k, batched));
+    std::vector<int> qts;
+    for (const Shape& sh : cands)
+        if (std::find(qts.begin(), qts.end(), sh.qt) == qts.end()) qts.push_back(sh.qt);
+    std::vector<std::vector<PairTiles>> pts;
+    std::vector<std::vector<int64_t>> firsts(qts.size());
+    for (size_t i = 0; i < qts.size(); ++i) pts.push_back(pair_tiles(J, P.order, qts[i], &firsts[i]));
+
     Uploader up;
     up.add(J.imgs);
     up.add(touts);
     up.add(train_list);
     up.add(pd);
-    up.add(items);
+    for (auto& t : pts) up.add(t);
     std::vector<const void*> d;
     RETCHK(upload_meta(c, up, d));
-    const ImgDev* dI = (const ImgDev*)d[0];
+    P.dI = (const ImgDev*)d[0];
     const TableOut* dTo = (const TableOut*)d[1];
     const int32_t* dTrain = (const int32_t*)d[2];
-    const PairDev* dP = (const PairDev*)d[3];
-    const Item* dItems = (const Item*)d[4];
-    MatchParams prm;
-    prm.k = c->cfg.k;
-    prm.tau = c->cfg.max_hamming;
-    prm.num2 = (int64_t)c->cfg.ratio_num * c->cfg.ratio_num;
-    prm.den2 = (int64_t)c->cfg.ratio_den * c->cfg.ratio_den;
-    prm.max_px = J.max_px;
+    P.dP = (const PairDev*)d[3];
+    P.prm.k = c->cfg.k;
+    P.prm.tau = c->cfg.max_hamming;
+    P.prm.num2 = (int64_t)c->cfg.ratio_num * c->cfg.ratio_num;
+    P.prm.den2 = (int64_t)c->cfg.ratio_den * c->cfg.ratio_den;
+    P.prm.max_px = J.max_px;
     unsigned long long* stats = c->dCount.as<unsigned long long>() + 8;
-    uint32_t* counter = reinterpret_cast<uint32_t*>(c->dCount.as<unsigned long long>() + 16);
-    HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
-    if (batched) {
-        HIPCHK(launch_bucket(c->stream, J.epi, dI, dTo, dTrain, (int)train_list.size()));
-        HIPCHK(launch_fill_u32(c->stream, counter, 1, 0u));
-        const int blocks_needed = (int)((items.size() + kWavesPerBlock - 1) / kWavesPerBlock);
-        const int grid = std::max(1, std::min(blocks_needed, c->n_cu * 7));
-        HIPCHK(hipEventRecord(c->ev0, c->stream));
-        HIPCHK(launch_match(c->stream, J.epi, grid, dI, dP, dItems, (int32_t)items.size(), counter, prm, J.o_idx,
-                            J.o_d1, J.o_d2, stats));
-        HIPCHK(hipEventRecord(c->ev1, c->stream));
-        c->last_launches += 1;
-    } else {
-        // plain form: per pair, the train image's tables (first use) and one
-        // matcher launch over that pair's query tiles
-        std::vector<char> built(n_img, 0);
-        HIPCHK(hipEventRecord(c->ev0, c->stream));
-        for (int64_t oi = 0; oi < n_pairs; ++oi) {
-            const int64_t p = order[oi];
-            const int t = J.pair_t[p];
-            if (!built[t]) {
-                built[t] = 1;
-                const int slot = (int)(std::find(train_list.begin(), train_list.end(), t) - train_list.begin());
-                HIPCHK(launch_bucket(c->stream, J.epi, dI, dTo, dTrain + slot, 1));
+    HIPCHK(launch_bucket(c->stream, J.epi, P.dI, dTo, dTrain, (int)train_list.size()));
+
+    Shape best = cands[0];
+    if (tune && cands.size() > 1) {
+        // time every candidate shape on a prefix of the pairs (outputs are
+        // identical for every shape; the full run rewrites them)
+        const int64_t sample_pairs = batched ? std::max<int64_t>(1, std::min<int64_t>(n_pairs, n_pairs / 16 + 8))
+                                             : std::min<int64_t>(n_pairs, 12);
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep)
+            for (const Shape& sh : cands) {
+                const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), sh.qt) - qts.begin());
+                const int64_t n_it = firsts[qi][sample_pairs];
+                item_costs(J, P.order, sh.qt, P.item_cost_prefix);
+                RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(),
+                                  firsts[qi][n_pairs]));
+                int64_t dummy_launches = 0;
+                HIPCHK(hipEventRecord(c->ev0, c->stream));
+                RETCHK(enqueue_matcher(c, P, J, sh, batched, firsts[qi], sample_pairs, n_it, stats, &dummy_launches));
+                HIPCHK(hipEventRecord(c->ev1, c->stream));
+                HIPCHK(hipEventSynchronize(c->ev1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                if (rep == 1 && ms < best_ms) {
+                    best_ms = ms;
+                    best = sh;
+                }
             }
-            const int64_t nit = item_begin[oi + 1] - item_begin[oi];
-            if (nit == 0) continue;
-            HIPCHK(launch_match(c->stream, J.epi, (int)((nit + kWavesPerBlock - 1) / kWavesPerBlock), dI, dP,
-                                dItems + item_begin[oi], (int32_t)nit, nullptr, prm, J.o_idx, J.o_d1, J.o_d2, stats));
-        }
-        HIPCHK(hipEventRecord(c->ev1, c->stream));
-        c->last_launches += n_pairs;
+        c->tuned[key] = best;
+        tune_cache_store(c, key, best);
+    } else if (tune) {
+        c->tuned[key] = best;
     }
+    const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), best.qt) - qts.begin());
+    const int64_t n_items = firsts[qi][n_pairs];
+    item_costs(J, P.order, best.qt, P.item_cost_prefix);
+    RETCHK(make_items(c, P, J, best.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(), n_items));
+    HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
+    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches));
+    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    c->last_shape_qt = best.qt;
+    c->last_shape_bpc = best.bpc;
     HIPCHK(hipMemcpyAsync(c->pin_small.p, stats, 24, hipMemcpyDeviceToHost, c->stream));
     return CASHASH_OK;
+}
+
+static void tune_cache_load(cashash_ctx* c) {
+    if (c->tune_loaded) return;
+    c->tune_loaded = true;
+    const char* path = std::getenv("CASHASH_AUTOTUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char key[256];
+        int qt = 0, bpc = 0;
+        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"qt\": %d, \"bpc\": %d}", key, &qt, &bpc) == 3 && qt > 0)
+            c->tuned[key] = Shape{qt, bpc};
+    }
+    std::fclose(f);
+}
+
+static void tune_cache_store(cashash_ctx* c, const std::string& key, Shape sh) {
+    (void)c;
+    const char* path = std::getenv("CASHASH_AUTOTUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"qt\": %d, \"bpc\": %d}\n", key.c_str(), sh.qt, sh.bpc);
+    std::fclose(f);
 }
 
 static int finish_match_job(cashash_ctx* c, MatchJob& J) {
@@ -772,13 +964,12 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
                       int32_t* o_d1, int32_t* o_d2, cashash_stats* stats) {
     const int M = im->n_images;
     const int64_t n_pairs = (int64_t)J.pair_q.size();
-    const size_t ent_bytes = J.epi ? sizeof(EntEpi) : sizeof(EntPlain);
     std::vector<int64_t> bytes(M), data_bytes(M);
     for (int m = 0; m < M; ++m) {
         const int n = im->n_feat[m];
         data_bytes[m] = (int64_t)slot_layout(n, true, J.epi).end;
         bytes[m] = data_bytes[m] + (int64_t)(al256((size_t)kTables * kOffStride * 4) +
-                                             al256((size_t)kTables * n * ent_bytes));
+                                             al256(ent_bytes(n, J.epi)));
     }
     // three image slots plus bucket tables for up to two blocks
     const int64_t budget = default_budget(c);
@@ -1037,6 +1228,8 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
         stats->bucket_entries = J.bucket_entries;
         stats->union_size = J.union_size;
         stats->ranked = J.ranked;
+        stats->tile_queries = c->last_shape_qt;
+        stats->blocks_per_cu = c->last_shape_bpc;
         stats->ms_match = now_ms() - t0;
     }
     return CASHASH_OK;

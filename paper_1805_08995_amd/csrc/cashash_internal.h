@@ -14,7 +14,9 @@ constexpr int kRows = kCodeBits + kTables * kKeyBits;  // 176 projection rows
 constexpr int kRowTiles = kRows / 16;                   // 11 MFMA row tiles
 constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
 constexpr int kMaxK = 64;
-constexpr int kListCap = 1024;     // per-wave LDS candidate list (u32 keys)
+constexpr int kListCap = 512;      // per-wave LDS candidate list (u32 keys); reused for tile distances
+constexpr int kSelCap = 512;       // per-wave LDS list of a query tile's kept candidates
+constexpr int kRegCap = 256;       // candidates held in registers (4 per lane) for the tie search
 constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
 
 // Per-image view.  desc/codes/keys/kp are the caller's (or staged) buffers;
@@ -40,22 +42,17 @@ struct CodeOut {
 // Writable bucket tables of one train image.
 struct TableOut {
     uint32_t* off;     // [6][257]
-    uint8_t* ent;      // [6][n] entries of kEntBytes<EPI>
+    uint8_t* ent;      // bucket-ordered entries, ent_bytes(n, epi)
 };
 
-// Bucket-ordered entry of table t: the train point's 128-bit code, its six
-// keys (bytes 0..5 of `kid`) and its index (bits 48..63), plus the keypoint
-// for the epipolar form.  Entries of one bucket are contiguous and in
-// ascending index order.
-struct EntPlain {
-    uint64_t c0, c1, kid;
-};
-struct EntEpi {
-    uint64_t c0, c1, kid;
-    float x, y;
-};
-template <bool EPI> struct EntOf { using T = EntPlain; };
-template <> struct EntOf<true> { using T = EntEpi; };
+// Bucket-ordered entries of a train image, struct of arrays over the six
+// tables: for table t and position s (entries of one bucket contiguous, in
+// ascending index order)
+//   code[t][s] : the point's 128-bit code (16 B)
+//   kid[t][s]  : its six keys in bytes 0..5 and its index in bits 48..63
+//   kp[t][s]   : its keypoint (epipolar form only)
+// laid out one after another from TableOut::ent / ImgDev::ent.
+inline __host__ __device__ size_t ent_bytes(int n, bool epi) { return (size_t)kTables * n * (epi ? 32 : 24); }
 
 struct PairDev {
     int32_t qi, ti;     // query image, train image
@@ -63,11 +60,16 @@ struct PairDev {
     double F[9];        // row-major fundamental matrix (epipolar form)
 };
 
-struct Item {           // a tile of consecutive queries of one pair
+struct Item {           // a tile of consecutive queries of one pair (nq <= 64, nq * k <= kSelCap)
     int32_t pair;
     int32_t q0;
     int32_t nq;
     int32_t pad;
+};
+
+struct PairTiles {      // pair `pair`'s query tiles are items [first, first + count)
+    int32_t pair;
+    int32_t first;
 };
 
 struct RowChunk {       // rows [r0, r0 + nr) of image img
@@ -77,12 +79,20 @@ struct RowChunk {       // rows [r0, r0 + nr) of image img
     int32_t pad;
 };
 
+constexpr int kSegments = 8;       // one work segment per XCD
+constexpr int kCounterStride = 64; // u32 elements between work counters (one 256-byte line each)
+
 struct MatchParams {
     int32_t k;
     int32_t tau;
     int64_t num2;       // ratio_num^2
     int64_t den2;       // ratio_den^2
     double max_px;
+    // persistent scheduling: items [seg[x], seg[x+1]) are segment x, handed
+    // out `grab` at a time from counter x; a wave starts on its own XCD's
+    // segment and moves to the others when it is exhausted
+    int32_t seg[kSegments + 1];
+    int32_t grab;
 };
 
 struct ProjParams {

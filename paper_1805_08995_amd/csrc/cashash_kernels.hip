@@ -27,6 +27,32 @@ __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Loads through pointers known to address global memory (pointers read from
+// device tables would otherwise be treated as generic and use flat loads).
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+#if __HIP_DEVICE_COMPILE__
+    return *(const __attribute__((address_space(1))) T*)(p);
+#else
+    return *p;  // host pass: parsed only, never run
+#endif
+}
+typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ ulonglong2 gload(const ulonglong2* p) {
+    const u64x2_t v = gload(reinterpret_cast<const u64x2_t*>(p));
+    return make_ulonglong2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 gload(const uint4* p) {
+    const u32x4_t v = gload(reinterpret_cast<const u32x4_t*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gload(const float2* p) {
+    const f32x2_t v = gload(reinterpret_cast<const f32x2_t*>(p));
+    return make_float2(v.x, v.y);
+}
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -50,6 +76,25 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Work items from the per-pair tile table: item i belongs to the last entry
+// whose first tile is <= i (binary search); its queries are tile (i - first)
+// of that pair's query image, qt per tile.
+__global__ void make_items_kernel(const PairTiles* __restrict__ pt, int32_t n_pt, const PairDev* __restrict__ pairs,
+                                  const ImgDev* __restrict__ imgs, int32_t qt, Item* __restrict__ items,
+                                  int32_t n_items) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    int32_t lo = 0, hi = n_pt - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (pt[mid].first <= i) lo = mid; else hi = mid - 1;
+    }
+    const int32_t p = pt[lo].pair;
+    const int32_t q0 = (i - pt[lo].first) * qt;
+    const int32_t nq = imgs[pairs[p].qi].n;
+    items[i] = Item{p, q0, min(qt, nq - q0), 0};
 }
 
 // ------------------------------------------------------------------ column sums
@@ -315,7 +360,6 @@ template <bool EPI>
 __global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ imgs,
                                                     const TableOut* __restrict__ touts,
                                                     const int32_t* __restrict__ train_list) {
-    using Ent = typename EntOf<EPI>::T;
     __shared__ uint32_t cnt[256];
     const int lane = threadIdx.x;
     const int m = train_list[blockIdx.x / kTables];
@@ -347,7 +391,9 @@ __global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ i
     }
     if (lane == 63) off[256] = incl;
     __syncthreads();
-    Ent* out = reinterpret_cast<Ent*>(to.ent) + (int64_t)t * n;
+    ulonglong2* out_code = reinterpret_cast<ulonglong2*>(to.ent) + (int64_t)t * n;
+    uint64_t* out_kid = reinterpret_cast<uint64_t*>(to.ent + (size_t)kTables * n * 16) + (int64_t)t * n;
+    float2* out_kp = reinterpret_cast<float2*>(to.ent + (size_t)kTables * n * 24) + (int64_t)t * n;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c = 0; c < n; c += 64) {
         const int j = c + lane;
@@ -366,15 +412,9 @@ __global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ i
         __syncthreads();
         if (valid) {
             const uint16_t* kp = reinterpret_cast<const uint16_t*>(im.keys + 6 * (int64_t)j);
-            Ent e;
-            e.c0 = im.codes[2 * (int64_t)j];
-            e.c1 = im.codes[2 * (int64_t)j + 1];
-            e.kid = (uint64_t)kp[0] | ((uint64_t)kp[1] << 16) | ((uint64_t)kp[2] << 32) | ((uint64_t)j << 48);
-            if constexpr (EPI) {
-                e.x = im.kp[2 * (int64_t)j];
-                e.y = im.kp[2 * (int64_t)j + 1];
-            }
-            out[pos] = e;
+            out_code[pos] = make_ulonglong2(im.codes[2 * (int64_t)j], im.codes[2 * (int64_t)j + 1]);
+            out_kid[pos] = (uint64_t)kp[0] | ((uint64_t)kp[1] << 16) | ((uint64_t)kp[2] << 32) | ((uint64_t)j << 48);
+            if constexpr (EPI) out_kp[pos] = make_float2(im.kp[2 * (int64_t)j], im.kp[2 * (int64_t)j + 1]);
             if (rank == 0) cnt[key] = pos + (uint32_t)__popcll(eq);
         }
         __syncthreads();
@@ -383,20 +423,44 @@ __global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ i
 
 // ------------------------------------------------------------------ matching
 
-// Smallest bin d of a 256-bin LDS histogram whose cumulative count reaches
-// `need` (need >= 1 and <= total); *below = count of bins < d.
+// x as seen through a DPP pattern; lanes whose source is outside their row,
+// or whose row is masked off, receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+    return __builtin_amdgcn_update_dpp(0u, x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS round trip).
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
+    x += dpp<0x111, 0xf>(x);  // row_shr:1
+    x += dpp<0x112, 0xf>(x);  // row_shr:2
+    x += dpp<0x114, 0xf>(x);  // row_shr:4
+    x += dpp<0x118, 0xf>(x);  // row_shr:8
+    x += dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    return (uint64_t)readlane((uint32_t)v, l) | ((uint64_t)readlane((uint32_t)(v >> 32), l) << 32);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) { return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), l)); }
+
+// Smallest bin d of the 256-bin LDS index table whose cumulative count
+// reaches `need` (1 <= need <= total); *below = count in bins < d.
 __device__ __forceinline__ uint32_t hist_select(const uint32_t* hist, uint32_t need, int lane, uint32_t* below) {
     const uint4 h = reinterpret_cast<const uint4*>(hist)[lane];
     const uint32_t s0 = h.x, s1 = s0 + h.y, s2 = s1 + h.z, s3 = s2 + h.w;
-    const uint32_t incl = wave_incl_scan(s3, lane);
+    const uint32_t incl = wave_scan_dpp(s3);
     const uint32_t ex = incl - s3;
-    const bool has = incl >= need;
     const uint32_t i = (ex + s0 >= need) ? 0u : (ex + s1 >= need) ? 1u : (ex + s2 >= need) ? 2u : 3u;
     const uint32_t bl = ex + (i == 0 ? 0u : i == 1 ? s0 : i == 2 ? s1 : s2);
-    const uint64_t m = __ballot(has);
+    const uint64_t m = __ballot(incl >= need);
     const int L = __ffsll((unsigned long long)m) - 1;
-    *below = uniform(__shfl(bl, L));
-    return uniform(__shfl(4u * (uint32_t)lane + i, L));
+    *below = readlane(bl, L);
+    return readlane(4u * (uint32_t)lane + i, L);
 }
 
 __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
@@ -414,35 +478,60 @@ struct QueryRuns {
     double la, lb, lc;
 };
 
+// Train image tables, struct of arrays (see ent_bytes).
+struct TrainView {
+    const ulonglong2* code;
+    const uint64_t* kid;
+    const float2* kp;
+    int32_t n;
+};
+
 // Candidate e of the concatenated six bucket runs -> packed key
-// (Hamming << 16 | index), or ~0u if it repeats an earlier table's candidate,
-// falls outside the epipolar band or exceeds tau.  n_union counts the
-// candidates that survive the union and the band.
+// (Hamming << 16 | index), or ~0u if e is past the runs, repeats an earlier
+// table's candidate, falls outside the epipolar band or exceeds tau.  The
+// loads are unconditional (a clamped position) so several calls can have
+// their loads in flight together.  n_union counts candidates that survive
+// the union and the band.
 template <bool EPI>
-__device__ __forceinline__ uint32_t key_at(uint32_t e, const typename EntOf<EPI>::T* __restrict__ ent, int32_t n_t,
-                                           const QueryRuns r, int32_t tau, double dd, uint32_t& n_union) {
-    using Ent = typename EntOf<EPI>::T;
-    if (e >= r.P6) return ~0u;
-    const uint32_t t = (uint32_t)(e >= r.P1) + (e >= r.P2) + (e >= r.P3) + (e >= r.P4) + (e >= r.P5);
+__device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, const QueryRuns& r, int32_t tau,
+                                           double dd, uint32_t& n_union) {
+    const bool in = e < r.P6;
+    const uint32_t ec = in ? e : 0u;
+    const uint32_t t = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
     const uint32_t Pt = t == 0 ? 0u : t == 1 ? r.P1 : t == 2 ? r.P2 : t == 3 ? r.P3 : t == 4 ? r.P4 : r.P5;
     const uint32_t bt = t == 0 ? r.b0 : t == 1 ? r.b1 : t == 2 ? r.b2 : t == 3 ? r.b3 : t == 4 ? r.b4 : r.b5;
-    const Ent* ep = ent + (int64_t)t * n_t + (bt + (e - Pt));
-    const uint64_t kid = ep->kid;
+    const int64_t pos = (int64_t)t * tv.n + (bt + (ec - Pt));
+    const ulonglong2 c = gload(tv.code + pos);
+    const uint64_t kid = gload(tv.kid + pos);
     bool dup = false;
 #pragma unroll
     for (int u = 0; u < kTables - 1; ++u) dup |= (u < (int)t) && (((kid ^ r.qk) >> (8 * u)) & 0xFFu) == 0;
-    if (dup) return ~0u;
+    bool ok = in && !dup;
     if constexpr (EPI) {
-        const double xp = (double)ep->x, yp = (double)ep->y;
+        const float2 p = gload(tv.kp + pos);
+        const double xp = (double)p.x, yp = (double)p.y;
         const double ev = (r.la * xp + r.lb * yp) + r.lc;
-        if (!(ev * ev <= dd * (r.la * r.la + r.lb * r.lb))) return ~0u;
+        ok = ok && (ev * ev <= dd * (r.la * r.la + r.lb * r.lb));
     }
-    ++n_union;
-    const uint32_t h = (uint32_t)(__popcll(ep->c0 ^ r.qc0) + __popcll(ep->c1 ^ r.qc1));
-    if ((int32_t)h > tau) return ~0u;
-    return (h << 16) | (uint32_t)(kid >> 48);
+    n_union += ok ? 1u : 0u;
+    const uint32_t h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
+    ok = ok && (int32_t)h <= tau;
+    return ok ? ((h << 16) | (uint32_t)(kid >> 48)) : ~0u;
 }
 
+// One wavefront per tile of <= 64 consecutive queries of one pair.
+//  setup    : lane l loads query l's code, keys and six bucket ranges at once;
+//             each query's values are then broadcast with readlane.
+//  Steps 1-3: per query, the six bucket runs are read four 64-wide chunks at
+//             a time (union by first-table dedupe, Hamming, tau, band); the
+//             index table (histogram over Hamming distance) is built in LDS
+//             and scanned to find the Hamming distance H* of the k-th
+//             candidate; ties at H* are broken by index by counting with
+//             ballots over a binary search of index bits.
+//  Step 4   : the tile's kept (query, candidate) pairs are measured together,
+//             4 lanes per pair with v_dot4_u32_u8; lane l then takes query l's
+//             distances, picks the nearest and second nearest and applies the
+//             ratio test, and the tile's outputs are stored coalesced.
 template <bool EPI>
 __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ imgs,
                                                     const PairDev* __restrict__ pairs,
@@ -451,209 +540,307 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                                                     int32_t* __restrict__ o_idx, int32_t* __restrict__ o_d1,
                                                     int32_t* __restrict__ o_d2,
                                                     unsigned long long* __restrict__ stats) {
-    using Ent = typename EntOf<EPI>::T;
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
-    __shared__ uint32_t s_list[kWavesPerBlock][kListCap];
-    __shared__ uint32_t s_sel[kWavesPerBlock][kMaxK];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
+    __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
+    const int lane = threadIdx.x & 63;
+    const int wv = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = s_hist[wv];
     uint32_t* list = s_list[wv];
     uint32_t* sel = s_sel[wv];
     const int part = lane & 3;
     uint64_t st_bucket = 0, st_ranked = 0;
     uint32_t st_union = 0;
-    uint64_t st_union64 = 0;
+    const double dd = prm.max_px * prm.max_px;
 
+    // XCD of this wavefront: its segment of the work list is the one whose
+    // train images stay in this XCD's L2
+    const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kSegments - 1);
     int32_t it = (int32_t)(blockIdx.x * kWavesPerBlock + wv);
+    int32_t cur = 0, end = 0;
     for (;;) {
         if (counter) {
-            uint32_t v = 0;
-            if (lane == 0) v = atomicAdd(counter, 1u);
-            it = (int32_t)uniform(__shfl(v, 0));
+            if (cur >= end) {
+                for (int sx = 0; sx < kSegments; ++sx) {
+                    const uint32_t x = (home + (uint32_t)sx) & (kSegments - 1);
+                    const int32_t s0 = prm.seg[x], s1 = prm.seg[x + 1];
+                    if (s0 >= s1) continue;
+                    uint32_t v = 0;
+                    if (lane == 0) v = atomicAdd(counter + x * kCounterStride, (uint32_t)prm.grab);
+                    v = readlane(v, 0);
+                    if ((int64_t)s0 + v < (int64_t)s1) {
+                        cur = s0 + (int32_t)v;
+                        end = min(cur + prm.grab, s1);
+                        break;
+                    }
+                }
+                if (cur >= end) break;  // every segment is exhausted
+            }
+            it = cur++;
         }
         if (it >= n_items) break;
         const Item item = items[it];
         const PairDev& pr = pairs[item.pair];
         const ImgDev Q = imgs[pr.qi];
         const ImgDev T = imgs[pr.ti];
-        const Ent* ent = reinterpret_cast<const Ent*>(T.ent);
-        const int32_t n_t = T.n;
-        const double dd = prm.max_px * prm.max_px;
-        double F[9];
-        if constexpr (EPI) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) F[i] = pr.F[i];
-        }
-        for (int32_t q = item.q0; q < item.q0 + item.nq; ++q) {
-            // ---- Step 1: the query's bucket in each table
-            QueryRuns qr;
-            qr.qc0 = Q.codes[2 * (int64_t)q];
-            qr.qc1 = Q.codes[2 * (int64_t)q + 1];
-            const uint16_t* kq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * (int64_t)q);
-            qr.qk = (uint64_t)kq[0] | ((uint64_t)kq[1] << 16) | ((uint64_t)kq[2] << 32);
-            uint32_t bs[kTables], ln[kTables];
+        TrainView tv;
+        tv.n = T.n;
+        tv.code = reinterpret_cast<const ulonglong2*>(T.ent);
+        tv.kid = reinterpret_cast<const uint64_t*>(T.ent + (size_t)kTables * T.n * 16);
+        tv.kp = reinterpret_cast<const float2*>(T.ent + (size_t)kTables * T.n * 24);
+        const int nq = (int)uniform((uint32_t)item.nq);
+        const int32_t q0 = (int32_t)uniform((uint32_t)item.q0);
+
+        // ---- setup, one lane per query of the tile
+        const int64_t lq = q0 + min(lane, nq - 1);
+        const uint64_t v_qc0 = gload(Q.codes + 2 * lq), v_qc1 = gload(Q.codes + 2 * lq + 1);
+        const uint16_t* kq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * lq);
+        const uint64_t v_qk = (uint64_t)gload(kq) | ((uint64_t)gload(kq + 1) << 16) | ((uint64_t)gload(kq + 2) << 32);
+        uint32_t v_b[kTables], v_P[kTables];
+        {
+            uint32_t acc = 0;
 #pragma unroll
             for (int t = 0; t < kTables; ++t) {
-                const uint32_t v = (uint32_t)((qr.qk >> (8 * t)) & 0xFFu);
-                bs[t] = T.off[t * kOffStride + v];
-                ln[t] = T.off[t * kOffStride + v + 1] - bs[t];
-            }
-            qr.b0 = bs[0]; qr.b1 = bs[1]; qr.b2 = bs[2]; qr.b3 = bs[3]; qr.b4 = bs[4]; qr.b5 = bs[5];
-            qr.P1 = ln[0];
-            qr.P2 = qr.P1 + ln[1];
-            qr.P3 = qr.P2 + ln[2];
-            qr.P4 = qr.P3 + ln[3];
-            qr.P5 = qr.P4 + ln[4];
-            qr.P6 = qr.P5 + ln[5];
-            const uint32_t total = qr.P6;
-            qr.la = qr.lb = qr.lc = 0.0;
-            if constexpr (EPI) {
-                const double x = (double)Q.kp[2 * (int64_t)q], y = (double)Q.kp[2 * (int64_t)q + 1];
-                qr.la = (F[0] * x + F[1] * y) + F[2];
-                qr.lb = (F[3] * x + F[4] * y) + F[5];
-                qr.lc = (F[6] * x + F[7] * y) + F[8];
-            }
-            st_bucket += total;
-
-            // ---- Steps 1-3 pass 1: union, Hamming, tau; index table over H
-            clear_hist(hist, lane);
-            uint32_t n_valid = 0;
-            for (uint32_t base = 0; base < total; base += 64) {
-                const uint32_t key = key_at<EPI>(base + lane, ent, n_t, qr, prm.tau, dd, st_union);
-                const bool keep = key != ~0u;
-                const uint64_t mk = __ballot(keep);
-                if (keep) {
-                    atomicAdd(&hist[key >> 16], 1u);
-                    const uint32_t slot = n_valid + mbcnt64(mk);
-                    if (slot < (uint32_t)kListCap) list[slot] = key;
-                }
-                n_valid += (uint32_t)__popcll(mk);
-            }
-            wave_sync();
-            const bool in_list = n_valid <= (uint32_t)kListCap;
-            const uint32_t span = in_list ? n_valid : total;
-            uint32_t dummy = 0;
-#define CAND(e) (in_list ? ((e) < n_valid ? list[(e)] : ~0u) : key_at<EPI>((e), ent, n_t, qr, prm.tau, dd, dummy))
-
-            const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
-            st_ranked += kk;
-            int32_t r_idx = -1, r_d1 = -1, r_d2 = -1;
-            if (kk > 0) {
-                // ---- Step 3: threshold of the kk-th key by counting passes
-                uint32_t below;
-                const uint32_t hs = hist_select(hist, kk, lane, &below);
-                uint32_t need = kk - below;
-                uint32_t ties = uniform(hist[hs]);
-                uint32_t bound;
-                if (ties == need) {
-                    bound = (hs + 1) << 16;
-                } else {
-                    clear_hist(hist, lane);
-                    for (uint32_t base = 0; base < span; base += 64) {
-                        const uint32_t key = CAND(base + lane);
-                        if ((key >> 16) == hs) atomicAdd(&hist[(key >> 8) & 0xFFu], 1u);
-                    }
-                    wave_sync();
-                    const uint32_t d1 = hist_select(hist, need, lane, &below);
-                    need -= below;
-                    ties = uniform(hist[d1]);
-                    const uint32_t prefix = (hs << 16) | (d1 << 8);
-                    if (ties == need) {
-                        bound = prefix + 256u;
-                    } else {
-                        clear_hist(hist, lane);
-                        for (uint32_t base = 0; base < span; base += 64) {
-                            const uint32_t key = CAND(base + lane);
-                            if ((key >> 8) == (prefix >> 8)) atomicAdd(&hist[key & 0xFFu], 1u);
-                        }
-                        wave_sync();
-                        const uint32_t d2 = hist_select(hist, need, lane, &below);
-                        bound = (prefix | d2) + 1u;
-                    }
-                }
-                // compaction: the kk keys below the bound
-                uint32_t nsel = 0;
-                for (uint32_t base = 0; base < span; base += 64) {
-                    const uint32_t key = CAND(base + lane);
-                    const bool keep = key < bound;
-                    const uint64_t mk = __ballot(keep);
-                    const uint32_t slot = nsel + mbcnt64(mk);
-                    if (keep && slot < (uint32_t)kMaxK) sel[slot] = key & 0xFFFFu;
-                    nsel += (uint32_t)__popcll(mk);
-                }
-                wave_sync();
-
-                // ---- Step 4: exact squared distances, 4 lanes per candidate
-                const uint8_t* qa = Q.desc + (int64_t)q * kDim + part * 32;
-                const uint4 a0 = reinterpret_cast<const uint4*>(qa)[0];
-                const uint4 a1 = reinterpret_cast<const uint4*>(qa)[1];
-                const uint32_t av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-                uint32_t aa = 0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) aa = __builtin_amdgcn_udot4(av[i], av[i], aa, false);
-                uint64_t best = ~0ull;
-                uint32_t sec = ~0u;
-                for (uint32_t r0 = 0; r0 < kk; r0 += 16) {
-                    const uint32_t s = r0 + (uint32_t)(lane >> 2);
-                    const bool act = s < kk;
-                    uint32_t j = 0, dp = 0;
-                    if (act) {
-                        j = min(sel[s], (uint32_t)(n_t - 1));  // ids come from the train image's tables
-                        const uint4* bp = reinterpret_cast<const uint4*>(T.desc + (int64_t)j * kDim + part * 32);
-                        const uint4 b0 = bp[0], b1 = bp[1];
-                        const uint32_t bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-                        uint32_t ab = 0, bb = 0;
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            ab = __builtin_amdgcn_udot4(av[i], bv[i], ab, false);
-                            bb = __builtin_amdgcn_udot4(bv[i], bv[i], bb, false);
-                        }
-                        dp = aa + bb - 2u * ab;
-                    }
-                    uint32_t d = dp + __shfl_xor(dp, 1);
-                    d += __shfl_xor(d, 2);
-                    if (act && part == 0) {
-                        const uint64_t c = ((uint64_t)d << 32) | j;
-                        if (c < best) {
-                            sec = min(sec, (uint32_t)(best >> 32));
-                            best = c;
-                        } else {
-                            sec = min(sec, d);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint64_t ob = __shfl_xor(best, off);
-                    const uint32_t os = __shfl_xor(sec, off);
-                    const uint32_t hi = max((uint32_t)(best >> 32), (uint32_t)(ob >> 32));
-                    sec = min(min(sec, os), hi);
-                    best = min(best, ob);
-                }
-                const int64_t D1 = (int64_t)(best >> 32);
-                r_d1 = (int32_t)D1;
-                if (kk >= 2) {
-                    const int64_t D2 = (int64_t)sec;
-                    r_d2 = (int32_t)D2;
-                    if (prm.den2 * D1 < prm.num2 * D2) r_idx = (int32_t)(uint32_t)best;
-                }
-            }
-#undef CAND
-            if (lane == 0) {
-                const int64_t o = pr.out + q;
-                o_idx[o] = r_idx;
-                o_d1[o] = r_d1;
-                o_d2[o] = r_d2;
+                const uint32_t v = (uint32_t)((v_qk >> (8 * t)) & 0xFFu);
+                v_b[t] = gload(T.off + t * kOffStride + v);
+                acc += gload(T.off + t * kOffStride + v + 1) - v_b[t];
+                v_P[t] = acc;
             }
         }
+        double v_la = 0.0, v_lb = 0.0, v_lc = 0.0;
+        if constexpr (EPI) {
+            const double x = (double)gload(Q.kp + 2 * lq), y = (double)gload(Q.kp + 2 * lq + 1);
+            v_la = (pr.F[0] * x + pr.F[1] * y) + pr.F[2];
+            v_lb = (pr.F[3] * x + pr.F[4] * y) + pr.F[5];
+            v_lc = (pr.F[6] * x + pr.F[7] * y) + pr.F[8];
+        }
+        uint32_t my_kk = 0, my_off = 0, sel_n = 0;
+        const uint32_t jbits = tv.n > 1 ? 32u - (uint32_t)__clz(tv.n - 1) : 0u;
+
+        for (int qi = 0; qi < nq; ++qi) {
+            QueryRuns qr;
+            qr.qc0 = readlane64(v_qc0, qi);
+            qr.qc1 = readlane64(v_qc1, qi);
+            qr.qk = readlane64(v_qk, qi);
+            qr.b0 = readlane(v_b[0], qi); qr.b1 = readlane(v_b[1], qi); qr.b2 = readlane(v_b[2], qi);
+            qr.b3 = readlane(v_b[3], qi); qr.b4 = readlane(v_b[4], qi); qr.b5 = readlane(v_b[5], qi);
+            qr.P1 = readlane(v_P[0], qi); qr.P2 = readlane(v_P[1], qi); qr.P3 = readlane(v_P[2], qi);
+            qr.P4 = readlane(v_P[3], qi); qr.P5 = readlane(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
+            if constexpr (EPI) {
+                qr.la = readlane_f64(v_la, qi);
+                qr.lb = readlane_f64(v_lb, qi);
+                qr.lc = readlane_f64(v_lc, qi);
+            } else {
+                qr.la = qr.lb = qr.lc = 0.0;
+            }
+            const uint32_t total = qr.P6;
+            st_bucket += total;
+
+            // ---- Steps 1-3, gather: union, Hamming, tau, band; index table
+            clear_hist(hist, lane);
+            uint32_t n_valid = 0;
+            uint32_t kr[4] = {~0u, ~0u, ~0u, ~0u};  // first 256 candidates in registers
+            for (uint32_t base = 0; base < total; base += 256) {
+                uint32_t kv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) kv[u] = key_at<EPI>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool keep = kv[u] != ~0u;
+                    const uint64_t mk = __ballot(keep);
+                    const uint32_t slot = n_valid + mbcnt64(mk);
+                    if (keep) {
+                        atomicAdd(&hist[kv[u] >> 16], 1u);
+                        if (slot < (uint32_t)kListCap) list[slot] = kv[u];
+                    }
+                    n_valid += (uint32_t)__popcll(mk);
+                }
+            }
+            wave_sync();
+            const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
+            st_ranked += kk;
+            if (lane == qi) {
+                my_kk = kk;
+                my_off = sel_n;
+            }
+            if (kk == 0) continue;
+            const bool in_regs = n_valid <= (uint32_t)kRegCap;
+            const bool in_list = n_valid <= (uint32_t)kListCap;
+            if (in_regs) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t e = 64u * u + lane;
+                    kr[u] = e < n_valid ? list[e] : ~0u;
+                }
+            }
+            const uint32_t span = in_list ? n_valid : total;
+            uint32_t dummy = 0;
+            // number of candidate keys in [lo, hi), counted with ballots
+#define COUNT_RANGE(lo, hi, c)                                                                        \
+    do {                                                                                              \
+        c = 0;                                                                                        \
+        if (in_regs) {                                                                                \
+            _Pragma("unroll") for (int u = 0; u < 4; ++u) c +=                                        \
+                (uint32_t)__popcll(__ballot(kr[u] >= (lo) && kr[u] < (hi)));                          \
+        } else {                                                                                      \
+            for (uint32_t base = 0; base < span; base += 64) {                                        \
+                const uint32_t e = base + lane;                                                       \
+                const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)                          \
+                                             : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);            \
+                c += (uint32_t)__popcll(__ballot(key >= (lo) && key < (hi)));                         \
+            }                                                                                         \
+        }                                                                                             \
+    } while (0)
+
+            // ---- Step 3: Hamming distance H* of the kk-th candidate from the index table
+            uint32_t below;
+            const uint32_t hs = hist_select(hist, kk, lane, &below);
+            const uint32_t need = kk - below;
+            const uint32_t ties = readlane(hist[hs], 0);
+            uint32_t tkey;  // kept candidates: key <= tkey
+            if (ties == need) {
+                tkey = ((hs + 1u) << 16) - 1u;
+            } else if (ties <= 64) {
+                // few ties: gather their indices (the index table is no longer
+                // needed) and rank each one against the others
+                const uint32_t lo = hs << 16, hi = lo + 0x10000u;
+                uint32_t nt = 0;
+                if (in_regs) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool tie = kr[u] >= lo && kr[u] < hi;
+                        const uint64_t mk = __ballot(tie);
+                        const uint32_t slot = nt + mbcnt64(mk);
+                        if (tie && slot < 256u) hist[slot] = kr[u] & 0xFFFFu;
+                        nt += (uint32_t)__popcll(mk);
+                    }
+                } else {
+                    for (uint32_t base = 0; base < span; base += 64) {
+                        const uint32_t e = base + lane;
+                        const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
+                                                     : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
+                        const bool tie = key >= lo && key < hi;
+                        const uint64_t mk = __ballot(tie);
+                        const uint32_t slot = nt + mbcnt64(mk);
+                        if (tie && slot < 256u) hist[slot] = key & 0xFFFFu;
+                        nt += (uint32_t)__popcll(mk);
+                    }
+                }
+                wave_sync();
+                const uint32_t jl = (uint32_t)lane < ties ? hist[lane] : ~0u;
+                uint32_t rank = 0;
+                for (uint32_t m = 0; m < ties; ++m) rank += hist[m] < jl ? 1u : 0u;
+                const uint64_t pick = __ballot((uint32_t)lane < ties && rank == need - 1u);
+                tkey = lo | readlane(jl, __ffsll((unsigned long long)pick) - 1);
+            } else {
+                // many ties: the need-th smallest index among them, by counting
+                // with ballots over a binary search of the index bits
+                const uint32_t lo = hs << 16;
+                uint32_t J = 0;
+                for (int b = (int)jbits - 1; b >= 0; --b) {
+                    const uint32_t J2 = J | (1u << b);
+                    uint32_t cnt;
+                    COUNT_RANGE(lo, lo | J2, cnt);
+                    if (cnt < need) J = J2;
+                }
+                tkey = lo | J;
+            }
+            // compaction of the kept candidates into the tile list
+            if (in_regs) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool keep = kr[u] <= tkey;
+                    const uint64_t mk = __ballot(keep);
+                    const uint32_t slot = sel_n + mbcnt64(mk);
+                    if (keep && slot < (uint32_t)kSelCap) sel[slot] = ((uint32_t)qi << 16) | (kr[u] & 0xFFFFu);
+                    sel_n += (uint32_t)__popcll(mk);
+                }
+            } else {
+                for (uint32_t base = 0; base < span; base += 64) {
+                    const uint32_t e = base + lane;
+                    const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
+                                                 : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
+                    const bool keep = key <= tkey;
+                    const uint64_t mk = __ballot(keep);
+                    const uint32_t slot = sel_n + mbcnt64(mk);
+                    if (keep && slot < (uint32_t)kSelCap) sel[slot] = ((uint32_t)qi << 16) | (key & 0xFFFFu);
+                    sel_n += (uint32_t)__popcll(mk);
+                }
+            }
+            wave_sync();
+        }
+#undef COUNT_RANGE
+        if (sel_n > (uint32_t)kSelCap) sel_n = kSelCap;  // cannot happen when nq * k <= kSelCap
+
+        // ---- Step 4: squared distances of all kept pairs of the tile, 4 lanes per pair
+        for (uint32_t p0 = 0; p0 < sel_n; p0 += 32) {
+            uint32_t dpv[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t p = p0 + 16u * h + (uint32_t)(lane >> 2);
+                const bool act = p < sel_n;
+                const uint32_t e = act ? sel[p] : 0u;
+                const uint32_t qi = e >> 16;
+                const uint32_t j = min(e & 0xFFFFu, (uint32_t)(tv.n - 1));
+                const uint4* ap = reinterpret_cast<const uint4*>(Q.desc + (int64_t)(q0 + (int)qi) * kDim + part * 32);
+                const uint4* bp = reinterpret_cast<const uint4*>(T.desc + (int64_t)j * kDim + part * 32);
+                const uint4 a0 = gload(ap), a1 = gload(ap + 1), b0 = gload(bp), b1 = gload(bp + 1);
+                const uint32_t av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                const uint32_t bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                uint32_t aa = 0, ab = 0, bb = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    aa = __builtin_amdgcn_udot4(av[i], av[i], aa, false);
+                    ab = __builtin_amdgcn_udot4(av[i], bv[i], ab, false);
+                    bb = __builtin_amdgcn_udot4(bv[i], bv[i], bb, false);
+                }
+                dpv[h] = aa + bb - 2u * ab;  // sum over this lane's 32 components of (a - b)^2
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t d = dpv[h] + dpp<0xB1, 0xf>(dpv[h]);  // quad_perm [1,0,3,2]
+                d += dpp<0x4E, 0xf>(d);                        // quad_perm [2,3,0,1]
+                const uint32_t p = p0 + 16u * h + (uint32_t)(lane >> 2);
+                if (part == 0 && p < sel_n) list[p] = d;
+            }
+        }
+        wave_sync();
+
+        // ---- nearest, second nearest and ratio test, one lane per query
+        if (lane < nq) {
+            uint64_t best = ~0ull;
+            uint32_t sec = ~0u;
+            for (uint32_t s = 0; s < my_kk; ++s) {
+                const uint32_t d = list[my_off + s];
+                const uint32_t j = sel[my_off + s] & 0xFFFFu;
+                const uint64_t c = ((uint64_t)d << 32) | j;
+                if (c < best) {
+                    sec = min(sec, (uint32_t)(best >> 32));
+                    best = c;
+                } else {
+                    sec = min(sec, d);
+                }
+            }
+            int32_t r_idx = -1, r_d1 = -1, r_d2 = -1;
+            if (my_kk >= 1) r_d1 = (int32_t)(best >> 32);
+            if (my_kk >= 2) {
+                r_d2 = (int32_t)sec;
+                if (prm.den2 * (int64_t)r_d1 < prm.num2 * (int64_t)r_d2) r_idx = (int32_t)(uint32_t)best;
+            }
+            const int64_t o = pr.out + q0 + lane;
+            o_idx[o] = r_idx;
+            o_d1[o] = r_d1;
+            o_d2[o] = r_d2;
+        }
+        wave_sync();
         if (!counter) break;
     }
-    // statistics: bucket entries (uniform per wave) and union sizes (per lane)
-    st_union64 = st_union;
-    for (int d = 32; d >= 1; d >>= 1) st_union64 += __shfl_xor(st_union64, d);
+    // statistics: bucket entries and ranked counts (uniform), union sizes (per lane)
+    uint64_t u64 = st_union;
+    for (int d = 32; d >= 1; d >>= 1) u64 += __shfl_xor(u64, d);
     if (lane == 0 && stats) {
         atomicAdd(&stats[0], (unsigned long long)st_bucket);
-        atomicAdd(&stats[1], (unsigned long long)st_union64);
+        atomicAdd(&stats[1], (unsigned long long)u64);
         atomicAdd(&stats[2], (unsigned long long)st_ranked);
     }
 }
@@ -675,6 +862,14 @@ hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsi
 hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, int64_t n, uint32_t v) {
     if (n <= 0) return hipSuccess;
     CH_LAUNCH(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipSuccess;
+}
+
+hipError_t launch_make_items(hipStream_t s, const PairTiles* pt, int32_t n_pt, const PairDev* pairs,
+                             const ImgDev* imgs, int32_t qt, Item* items, int32_t n_items) {
+    if (n_items <= 0) return hipSuccess;
+    CH_LAUNCH(make_items_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, pt, n_pt, pairs, imgs, qt,
+              items, n_items);
     return hipSuccess;
 }
 

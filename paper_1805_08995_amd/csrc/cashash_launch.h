@@ -5,6 +5,8 @@
 namespace cashash {
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, int64_t n, unsigned long long v);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, int64_t n, uint32_t v);
+hipError_t launch_make_items(hipStream_t s, const PairTiles* pt, int32_t n_pt, const PairDev* pairs,
+                             const ImgDev* imgs, int32_t qt, Item* items, int32_t n_items);
 hipError_t launch_colsum(hipStream_t s, const ImgDev* imgs, const RowChunk* chunks, int n_chunks,
                          unsigned long long* S);
 hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long* S, double n_tot, float* bias);
