@@ -25,6 +25,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one full matcher launch on this workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy (x2.0 and x1.0); see
+# profiles/match_kernel_scenes_100x8000.md.  Valid only for the kernel source
+# they were taken on.
+MEASURED_TRAFFIC = {"kernels_sha256": "80d70e1babf4d2c76169d68ce8e6aa1bf2ce0bf60b5d85e799475c79e2a00d5c",
+                    "workload": "scenes_100x8000_exhaustive_4950pairs",
+                    "fetch_bytes": 4381058 * 1024 * 2, "write_bytes": 479123 * 1024}
+
+
+def measured_traffic(workload):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1805_08995_amd", "csrc", "cashash_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    t = MEASURED_TRAFFIC
+    if sha != t["kernels_sha256"] or workload != t["workload"]:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -92,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
@@ -102,6 +122,15 @@ def main():
     from paper_1805_08995_amd import binding, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 1 << 30
+        x = torch.ones(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "dispatches": 3}), flush=True)
+        return
     binding.lib()
 
     log(f"generating {args.images} images x {args.feats} features")
@@ -153,7 +182,8 @@ def main():
                    "n_images": args.images, "n_feat": args.feats, "pairs": n_pairs, "k": 10, "ratio": 0.8,
                    "form": "batched bf16 hi+lo MFMA projection, one persistent matcher launch"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"),
                      "kernel": "match_kernel<false>", "kernel_ms": round(kernel_ms, 4),
                      "algorithmic_bytes_per_launch": int(abytes)},
         "stats": {"near_margin_recomputes": st_codes["near_margin_recomputes"],
