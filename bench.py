@@ -184,7 +184,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"),
-                     "kernel": "match_kernel<false>", "kernel_ms": round(kernel_ms, 4),
+                     "kernel": "match_kernel<false, 4>", "kernel_ms": round(kernel_ms, 4),
+                     "note": ("achieved = algorithmic (touched) bytes of the byte model / kernel time; "
+                              "frac > 1 means the working set is re-read from L2/LDS (cache reuse); "
+                              "traffic = measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)"),
                      "algorithmic_bytes_per_launch": int(abytes)},
         "stats": {"near_margin_recomputes": st_codes["near_margin_recomputes"],
                   "bucket_entries_per_query": round(st_match["bucket_entries"] / st_match["queries"], 2),

@@ -87,6 +87,7 @@ typedef struct {
     int64_t h2d_bytes, d2h_bytes, image_loads;
     int64_t tile_queries;           /* matcher launch shape used: queries per work item, */
     int64_t blocks_per_cu;          /*   persistent blocks per compute unit (0 in the plain form) */
+    int64_t graph_replayed;         /* 1 if the batched matcher ran as a replay of a captured HIP graph */
     double ms_codes, ms_match;      /* wall time of the call */
 } cashash_stats;
 

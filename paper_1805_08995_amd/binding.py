@@ -44,7 +44,7 @@ class Stats(C.Structure):
     _fields_ = [("pairs", C.c_int64), ("queries", C.c_int64), ("bucket_entries", C.c_int64),
                 ("union_size", C.c_int64), ("ranked", C.c_int64), ("near_margin_recomputes", C.c_int64),
                 ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("image_loads", C.c_int64),
-                ("tile_queries", C.c_int64), ("blocks_per_cu", C.c_int64),
+                ("tile_queries", C.c_int64), ("blocks_per_cu", C.c_int64), ("graph_replayed", C.c_int64),
                 ("ms_codes", C.c_double), ("ms_match", C.c_double)]
 
     def as_dict(self):

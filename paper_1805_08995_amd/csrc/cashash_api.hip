@@ -132,10 +132,13 @@ struct cashash_ctx {
     int n_cu = 256;
     std::vector<double> R64;  // [176][128]
     DevBuf dR64, dR32, dFrag, dBias, dS, dCount;
-    DevBuf meta[2];           // uploaded tables (images, pairs, items, tiles ...), double-buffered
-    HostPinned meta_host[2];
-    hipEvent_t meta_ev[2] = {nullptr, nullptr};
-    int meta_turn = 0;
+    // uploaded tables (images, pairs, tiles ...): one double-buffered area for
+    // the code builder and one for the matcher, so that the matcher's table
+    // addresses (baked into captured launches) do not move between calls
+    DevBuf meta[2][2];
+    HostPinned meta_host[2][2];
+    hipEvent_t meta_ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int meta_turn[2] = {0, 0};
     DevBuf near, tables;      // near-margin masks; bucket tables
     DevBuf stage, outbuf;     // host-memory mode: resident image slots; per-step outputs
     HostPinned pin[2];        // host-memory mode upload staging
@@ -148,6 +151,17 @@ struct cashash_ctx {
     double last_ms = 0.0;
     int64_t last_launches = 0;
     DevBuf items;             // matcher work items of the current job
+    // captured persistent-matcher launches, keyed by their launch arguments
+    struct GraphEntry {
+        std::string key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    bool use_graphs = true;
+    int64_t graph_replays = 0;
+    bool last_replayed = false;
     DevBuf counters;          // per-segment work counters of the persistent matcher
     std::map<std::string, Shape> tuned;
     bool tune_loaded = false;
@@ -244,15 +258,19 @@ static void destroy_ctx(cashash_ctx* c) {
         hipStreamSynchronize(c->copy_stream);
         hipStreamDestroy(c->copy_stream);
     }
-    for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0], &c->meta[1],
-                      &c->near, &c->tables, &c->stage, &c->outbuf, &c->items, &c->counters})
+    for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
+                      &c->meta[1][0], &c->meta[1][1], &c->near, &c->tables, &c->stage, &c->outbuf, &c->items,
+                      &c->counters})
         b->release();
-    for (HostPinned* h : {&c->meta_host[0], &c->meta_host[1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
+    for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
+                          &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
         h->release();
-    for (hipEvent_t e : {c->ev0, c->ev1, c->meta_ev[0], c->meta_ev[1], c->pin_ev[0], c->pin_ev[1],
+    for (hipEvent_t e : {c->ev0, c->ev1, c->meta_ev[0][0], c->meta_ev[0][1], c->meta_ev[1][0], c->meta_ev[1][1],
+                         c->pin_ev[0], c->pin_ev[1],
                          c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
                          c->slot_free_ev[1], c->slot_free_ev[2]})
         if (e) hipEventDestroy(e);
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
     delete c;
 }
@@ -311,12 +329,17 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess)
         return bail(fail(CASHASH_E_DEVICE, "hipGetDeviceProperties failed"));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    {
+        const char* g = std::getenv("CASHASH_GRAPHS");
+        c->use_graphs = !(g && g[0] == '0');
+    }
     int r = cashash_set_config(c, &n);
     if (r) return bail(r);
     if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
         return bail(fail(CASHASH_E_DEVICE, "stream/event creation failed"));
-    for (hipEvent_t* e : {&c->meta_ev[0], &c->meta_ev[1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
+    for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1], &c->pin_ev[0],
+                          &c->pin_ev[1], &c->slot_load_ev[0],
                           &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
                           &c->slot_free_ev[2]})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
@@ -352,17 +375,22 @@ static double now_ms() {
 // Uploads small tables on the compute stream (so they follow the kernels that
 // read the previous contents).  Two buffers alternate; a buffer's pinned
 // source is rewritten only after its previous copy has completed.
-static int upload_meta(cashash_ctx* c, Uploader& up, std::vector<const void*>& dptr) {
-    const int b = c->meta_turn;
-    c->meta_turn ^= 1;
-    HIPCHK(hipEventSynchronize(c->meta_ev[b]));
-    RETCHK(c->meta[b].ensure(up.host.size()));
-    RETCHK(c->meta_host[b].ensure(up.host.size()));
-    std::memcpy(c->meta_host[b].p, up.host.data(), up.host.size());
-    HIPCHK(hipMemcpyAsync(c->meta[b].p, c->meta_host[b].p, up.host.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->meta_ev[b], c->stream));
+enum { kMetaCodes = 0, kMetaMatch = 1 };
+
+static int upload_meta(cashash_ctx* c, Uploader& up, std::vector<const void*>& dptr, int area) {
+    const int b = c->meta_turn[area];
+    c->meta_turn[area] ^= 1;
+    HIPCHK(hipEventSynchronize(c->meta_ev[area][b]));
+    DevBuf& dev = c->meta[area][b];
+    HostPinned& host = c->meta_host[area][b];
+    const size_t need = up.host.size();
+    if (need > dev.cap) RETCHK(dev.ensure(std::max<size_t>({need, 2 * dev.cap, (size_t)1 << 20})));
+    if (need > host.cap) RETCHK(host.ensure(std::max<size_t>({need, 2 * host.cap, (size_t)1 << 20})));
+    std::memcpy(host.p, up.host.data(), need);
+    HIPCHK(hipMemcpyAsync(dev.p, host.p, need, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->meta_ev[area][b], c->stream));
     dptr.clear();
-    for (size_t o : up.offs) dptr.push_back(c->meta[b].as<uint8_t>() + o);
+    for (size_t o : up.offs) dptr.push_back(dev.as<uint8_t>() + o);
     return CASHASH_OK;
 }
 
@@ -395,7 +423,7 @@ static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
     up.add(imgs);
     up.add(chunks);
     std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d));
+    RETCHK(upload_meta(c, up, d, kMetaCodes));
     HIPCHK(launch_colsum(c->stream, (const ImgDev*)d[0], (const RowChunk*)d[1], (int)chunks.size(),
                          c->dS.as<unsigned long long>()));
     return CASHASH_OK;
@@ -417,7 +445,7 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     up.add(outs);
     up.add(tiles);
     std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d));
+    RETCHK(upload_meta(c, up, d, kMetaCodes));
     const ImgDev* dI = (const ImgDev*)d[0];
     const CodeOut* dO = (const CodeOut*)d[1];
     const RowChunk* dT = (const RowChunk*)d[2];
@@ -552,19 +580,45 @@ struct MatchPlan {
     const PairDev* dP = nullptr;
     MatchParams prm{};
     std::vector<int64_t> order;
-    std::vector<int64_t> item_cost_prefix;  // estimated cost of items [0, i) for the current shape
 };
 
-// Estimated cost of each item (its queries times its train image's size),
-// as a prefix sum in item order.
-static void item_costs(const MatchJob& J, const std::vector<int64_t>& order, int qt, std::vector<int64_t>& pre) {
-    pre.assign(1, 0);
-    for (int64_t p : order) {
-        const int nq = J.imgs[J.pair_q[p]].n;
-        const int64_t nt = std::max(1, J.imgs[J.pair_t[p]].n);
-        for (int q0 = 0; q0 < nq; q0 += qt) pre.push_back(pre.back() + (int64_t)std::min(qt, nq - q0) * nt);
+// Segment boundaries (in items) that split the estimated cost (queries x
+// train size) of the first n_run items, taken in pair order, into kSegments
+// nearly equal parts.  Costs are summed per pair; inside a pair every tile
+// but the last has qt queries.
+static void segment_bounds(const MatchJob& J, const std::vector<int64_t>& order, const std::vector<int64_t>& first_of,
+                           int qt, int64_t oi_lo, int64_t oi_hi, int64_t item_lo, int64_t item_hi, int32_t* seg) {
+    // items are relative to item_lo in the result
+    const int64_t n_run = item_hi - item_lo;
+    std::vector<double> cum((size_t)(oi_hi - oi_lo) + 1, 0.0);
+    for (int64_t oi = oi_lo; oi < oi_hi; ++oi) {
+        const int64_t p = order[oi];
+        const int64_t lo = first_of[oi], hi = std::min(first_of[oi + 1], item_hi);
+        const double nq_run = hi > lo ? std::min<double>(J.imgs[J.pair_q[p]].n, (double)(hi - lo) * qt) : 0.0;
+        cum[oi - oi_lo + 1] = cum[oi - oi_lo] + nq_run * std::max(1, J.imgs[J.pair_t[p]].n);
     }
+    const double total = cum.back();
+    for (int x = 0; x <= kSegments; ++x) {
+        const double target = total * x / kSegments;
+        const size_t k = (size_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+        int64_t item = 0;
+        if (k > 0) {
+            // inside pair k-1 of the range: place the boundary proportionally to its cost
+            const int64_t oi = oi_lo + (int64_t)k - 1;
+            const double c0 = cum[k - 1], c1 = cum[k];
+            const int64_t lo = first_of[oi] - item_lo, hi = std::min(first_of[oi + 1], item_hi) - item_lo;
+            const double f = c1 > c0 ? (target - c0) / (c1 - c0) : 1.0;
+            item = lo + (int64_t)std::llround(f * (double)(hi - lo));
+        }
+        seg[x] = (int32_t)std::min<int64_t>(std::max<int64_t>(item, 0), n_run);
+    }
+    seg[0] = 0;
+    seg[kSegments] = (int32_t)n_run;
+    for (int x = 1; x <= kSegments; ++x) seg[x] = std::max(seg[x], seg[x - 1]);
 }
+
+// Register slots of the matcher instantiation a pair runs in.
+static int slots_for(const MatchJob& J, int64_t p) { return J.imgs[J.pair_t[p]].n > kLargeTrain ? 8 : 4; }
 
 // Generate the work items of shape qt on the device (into c->items).
 static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int qt, const PairTiles* dPT,
@@ -579,36 +633,105 @@ static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int
 // in the plain form, one launch per pair over its own items.
 static int enqueue_matcher(cashash_ctx* c, const MatchPlan& P, MatchJob& J, Shape sh, bool batched,
                            const std::vector<int64_t>& first_of, int64_t n_pairs_run, int64_t n_items,
-                           unsigned long long* stats, int64_t* launches) {
+                           unsigned long long* stats, int64_t* launches, bool use_graph) {
     uint32_t* counter = c->counters.as<uint32_t>();
     const Item* items = c->items.as<Item>();
     if (batched) {
-        HIPCHK(launch_fill_u32(c->stream, counter, kSegments * kCounterStride, 0u));
-        const int blocks_needed = (int)((n_items + kWavesPerBlock - 1) / kWavesPerBlock);
-        const int grid = std::max(1, std::min(blocks_needed, c->n_cu * sh.bpc));
-        MatchParams prm = P.prm;
-        // segments of about equal estimated cost (queries x train size), one per XCD
-        const std::vector<int64_t>& cost = P.item_cost_prefix;
-        const int64_t items_total = (int64_t)cost.size() - 1;
-        const int64_t n_run = std::min<int64_t>(n_items, items_total);
-        for (int x = 0; x <= kSegments; ++x) {
-            const double target = (double)cost[n_run] * x / kSegments;
-            const int64_t pos = std::lower_bound(cost.begin(), cost.begin() + n_run + 1, (int64_t)std::ceil(target)) -
-                                cost.begin();
-            prm.seg[x] = (int32_t)std::min<int64_t>(pos, n_run);
+        // one persistent launch per register-slot group (pairs are ordered
+        // small-train group first), each over its own item range
+        struct Launch {
+            int ns, grid;
+            int64_t item_lo, n;
+            MatchParams prm;
+        };
+        std::vector<Launch> ls;
+        int64_t oi = 0;
+        while (oi < n_pairs_run) {
+            const int ns = slots_for(J, P.order[oi]);
+            int64_t oe = oi;
+            while (oe < n_pairs_run && slots_for(J, P.order[oe]) == ns) ++oe;
+            const int64_t ilo = first_of[oi], ihi = std::min(first_of[oe], n_items);
+            if (ihi > ilo) {
+                Launch L;
+                L.ns = ns;
+                L.item_lo = ilo;
+                L.n = ihi - ilo;
+                const int blocks_needed = (int)((L.n + kWavesPerBlock - 1) / kWavesPerBlock);
+                L.grid = std::max(1, std::min(blocks_needed, c->n_cu * sh.bpc));
+                L.prm = P.prm;
+                // segments of about equal estimated cost (queries x train size), one per XCD
+                segment_bounds(J, P.order, first_of, sh.qt, oi, oe, ilo, ihi, L.prm.seg);
+                const int64_t waves = (int64_t)L.grid * kWavesPerBlock;
+                L.prm.grab = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, L.n / std::max<int64_t>(1, waves * 64)));
+                ls.push_back(L);
+            }
+            oi = oe;
         }
-        prm.seg[0] = 0;
-        prm.seg[kSegments] = (int32_t)n_run;
-        const int64_t waves = (int64_t)grid * kWavesPerBlock;
-        prm.grab = (int32_t)std::max<int64_t>(1, std::min<int64_t>(8, n_run / std::max<int64_t>(1, waves * 64)));
-        HIPCHK(launch_match(c->stream, J.epi, grid, P.dI, P.dP, items, (int32_t)n_run, counter, prm, J.o_idx,
-                            J.o_d1, J.o_d2, stats));        *launches += 1;
+        auto issue = [&]() -> hipError_t {
+            for (const Launch& L : ls) {
+                hipError_t e = launch_fill_u32(c->stream, counter, kSegments * kCounterStride, 0u);
+                if (e == hipSuccess)
+                    e = launch_match(c->stream, J.epi, L.ns, L.grid, P.dI, P.dP, items + L.item_lo, (int32_t)L.n,
+                                     counter, L.prm, J.o_idx, J.o_d1, J.o_d2, stats);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        c->last_replayed = false;
+        if (use_graph && c->use_graphs && !ls.empty()) {
+            // counter resets + persistent launches as one captured graph,
+            // replayed while the launch arguments are unchanged
+            std::string key;
+            auto put = [&key](const void* v, size_t n) { key.append(static_cast<const char*>(v), n); };
+            const int epi = J.epi ? 1 : 0;
+            const void* ptrs[] = {P.dI, P.dP, items, counter, J.o_idx, J.o_d1, J.o_d2, stats};
+            put(&epi, sizeof epi);
+            put(ptrs, sizeof ptrs);
+            for (const Launch& L : ls) {
+                put(&L.ns, sizeof L.ns);
+                put(&L.grid, sizeof L.grid);
+                put(&L.item_lo, sizeof L.item_lo);
+                put(&L.n, sizeof L.n);
+                put(&L.prm, sizeof L.prm);
+            }
+            hipGraphExec_t exec = nullptr;
+            for (auto& g : c->graphs)
+                if (g.key == key) {
+                    exec = g.exec;
+                    g.used = ++c->graph_clock;
+                    c->graph_replays++;
+                    c->last_replayed = true;
+                }
+            if (!exec) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                const hipError_t e1 = issue();
+                const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+                HIPCHK(e1);
+                HIPCHK(e2);
+                const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                HIPCHK(e3);
+                if (c->graphs.size() >= 4) {
+                    auto old = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                                [](const auto& a, const auto& b) { return a.used < b.used; });
+                    hipGraphExecDestroy(old->exec);
+                    c->graphs.erase(old);
+                }
+                c->graphs.push_back({key, exec, ++c->graph_clock});
+            }
+            HIPCHK(hipGraphLaunch(exec, c->stream));
+        } else {
+            HIPCHK(issue());
+        }
+        *launches += (int64_t)ls.size();
     } else {
         for (int64_t oi = 0; oi < n_pairs_run; ++oi) {
             const int64_t nit = first_of[oi + 1] - first_of[oi];
             if (nit == 0) continue;
-            HIPCHK(launch_match(c->stream, J.epi, (int)((nit + kWavesPerBlock - 1) / kWavesPerBlock), P.dI, P.dP,
-                                items + first_of[oi], (int32_t)nit, nullptr, P.prm, J.o_idx, J.o_d1, J.o_d2, stats));
+            HIPCHK(launch_match(c->stream, J.epi, slots_for(J, P.order[oi]),
+                                (int)((nit + kWavesPerBlock - 1) / kWavesPerBlock), P.dI, P.dP, items + first_of[oi],
+                                (int32_t)nit, nullptr, P.prm, J.o_idx, J.o_d1, J.o_d2, stats));
             *launches += 1;
         }
     }
@@ -663,8 +786,10 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     std::iota(P.order.begin(), P.order.end(), 0);
     const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     if (batched)
-        std::stable_sort(P.order.begin(), P.order.end(),
-                         [&](int64_t a, int64_t b) { return J.pair_t[a] < J.pair_t[b]; });
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int64_t a, int64_t b) {
+            const int sa = slots_for(J, a), sb = slots_for(J, b);
+            return sa != sb ? sa < sb : J.pair_t[a] < J.pair_t[b];
+        });
     // launch shapes: cached, tuned now, or the default
     tune_cache_load(c);
     const std::string key = tune_key(batched, J.epi, c->cfg.k, n_pairs ? sum_nt / n_pairs : 0.0,
@@ -692,7 +817,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     up.add(pd);
     for (auto& t : pts) up.add(t);
     std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d));
+    RETCHK(upload_meta(c, up, d, kMetaMatch));
     P.dI = (const ImgDev*)d[0];
     const TableOut* dTo = (const TableOut*)d[1];
     const int32_t* dTrain = (const int32_t*)d[2];
@@ -716,12 +841,12 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
             for (const Shape& sh : cands) {
                 const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), sh.qt) - qts.begin());
                 const int64_t n_it = firsts[qi][sample_pairs];
-                item_costs(J, P.order, sh.qt, P.item_cost_prefix);
                 RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(),
                                   firsts[qi][n_pairs]));
                 int64_t dummy_launches = 0;
                 HIPCHK(hipEventRecord(c->ev0, c->stream));
-                RETCHK(enqueue_matcher(c, P, J, sh, batched, firsts[qi], sample_pairs, n_it, stats, &dummy_launches));
+                RETCHK(enqueue_matcher(c, P, J, sh, batched, firsts[qi], sample_pairs, n_it, stats, &dummy_launches,
+                                       false));
                 HIPCHK(hipEventRecord(c->ev1, c->stream));
                 HIPCHK(hipEventSynchronize(c->ev1));
                 float ms = 0.f;
@@ -738,11 +863,10 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     }
     const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), best.qt) - qts.begin());
     const int64_t n_items = firsts[qi][n_pairs];
-    item_costs(J, P.order, best.qt, P.item_cost_prefix);
     RETCHK(make_items(c, P, J, best.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(), n_items));
     HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches));
+    RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches, true));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->last_shape_qt = best.qt;
     c->last_shape_bpc = best.bpc;
@@ -1206,6 +1330,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
     }
     if (total_q > 0 && (!o_idx || !o_d1 || !o_d2)) return fail(CASHASH_E_INVAL, "null output arrays");
     c->last_launches = 0;
+    c->last_replayed = false;
     if (c->cfg.mem == CASHASH_MEM_DEVICE) {
         if (misaligned(o_idx, 4) || misaligned(o_d1, 4) || misaligned(o_d2, 4))
             return fail(CASHASH_E_INVAL, "misaligned output arrays");
@@ -1230,6 +1355,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
         stats->ranked = J.ranked;
         stats->tile_queries = c->last_shape_qt;
         stats->blocks_per_cu = c->last_shape_bpc;
+        stats->graph_replayed = c->last_replayed ? 1 : 0;
         stats->ms_match = now_ms() - t0;
     }
     return CASHASH_OK;

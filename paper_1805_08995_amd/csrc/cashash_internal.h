@@ -16,7 +16,12 @@ constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
 constexpr int kMaxK = 64;
 constexpr int kListCap = 512;      // per-wave LDS candidate list (u32 keys); reused for tile distances
 constexpr int kSelCap = 512;       // per-wave LDS list of a query tile's kept candidates
-constexpr int kRegCap = 256;       // candidates held in registers (4 per lane) for the tie search
+// A query's candidate keys are held in NS 64-wide register slots (NS = 4 or
+// 8, a template parameter of the matcher); queries with more candidates use
+// the LDS list.  Pairs whose train image has more than kLargeTrain points run
+// in the 8-slot instantiation, the rest in the 4-slot one (fewer registers,
+// more resident waves).
+constexpr int kLargeTrain = 9000;
 constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
 
 // Per-image view.  desc/codes/keys/kp are the caller's (or staged) buffers;

@@ -473,8 +473,8 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
 // its epipolar line.  Passed by value so every field stays in registers.
 struct QueryRuns {
     uint64_t qc0, qc1, qk;
-    uint32_t b0, b1, b2, b3, b4, b5;
     uint32_t P1, P2, P3, P4, P5, P6;
+    uint32_t cvec;  // lane u < 6 holds C_u = u * n_t + b_u - P_u: candidate e of table t sits at entry e + C_t
     double la, lb, lc;
 };
 
@@ -492,31 +492,53 @@ struct TrainView {
 // loads are unconditional (a clamped position) so several calls can have
 // their loads in flight together.  n_union counts candidates that survive
 // the union and the band.
-template <bool EPI>
-__device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, const QueryRuns& r, int32_t tau,
-                                           double dd, uint32_t& n_union) {
-    const bool in = e < r.P6;
-    const uint32_t ec = in ? e : 0u;
-    const uint32_t t = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
-    const uint32_t Pt = t == 0 ? 0u : t == 1 ? r.P1 : t == 2 ? r.P2 : t == 3 ? r.P3 : t == 4 ? r.P4 : r.P5;
-    const uint32_t bt = t == 0 ? r.b0 : t == 1 ? r.b1 : t == 2 ? r.b2 : t == 3 ? r.b3 : t == 4 ? r.b4 : r.b5;
-    const int64_t pos = (int64_t)t * tv.n + (bt + (ec - Pt));
+// Table t and entry position of candidate e of the concatenated runs; lanes
+// past the runs get candidate 0's position (a valid address).
+__device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, uint32_t& t) {
+    const uint32_t ec = e < r.P6 ? e : 0u;
+    t = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
+    return ec + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(t << 2), (int)r.cvec);
+}
+
+// Eq. 1-2: the candidate's keypoint lies within the band around the
+// query's epipolar line.
+__device__ __forceinline__ bool in_band(const TrainView& tv, uint32_t pos, const QueryRuns& r, double dd) {
+    const float2 p = gload(tv.kp + pos);
+    const double xp = (double)p.x, yp = (double)p.y;
+    const double ev = (r.la * xp + r.lb * yp) + r.lc;
+    return ev * ev <= dd * (r.la * r.la + r.lb * r.lb);
+}
+
+// Entry (t, pos) -> packed key (Hamming << 16 | index), or ~0u if it repeats
+// an earlier table's candidate or exceeds tau.  `live` masks lanes with no
+// candidate; n_union counts candidates that survive the union.
+__device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t t, uint32_t pos, bool live,
+                                              const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     const ulonglong2 c = gload(tv.code + pos);
     const uint64_t kid = gload(tv.kid + pos);
-    bool dup = false;
-#pragma unroll
-    for (int u = 0; u < kTables - 1; ++u) dup |= (u < (int)t) && (((kid ^ r.qk) >> (8 * u)) & 0xFFu) == 0;
-    bool ok = in && !dup;
-    if constexpr (EPI) {
-        const float2 p = gload(tv.kp + pos);
-        const double xp = (double)p.x, yp = (double)p.y;
-        const double ev = (r.la * xp + r.lb * yp) + r.lc;
-        ok = ok && (ev * ev <= dd * (r.la * r.la + r.lb * r.lb));
-    }
+    // union: drop the candidate if it shares an earlier table's key with the
+    // query (it was already collected there).  Zero bytes of x = keys ^ qkeys
+    // are found with the carry-free test ((x & 0x7f..) + 0x7f..) | x.
+    const uint64_t x = (kid ^ r.qk) & 0xFFFFFFFFFFFFull;
+    const uint64_t zb = ~(((x & 0x7F7F7F7F7F7Full) + 0x7F7F7F7F7F7Full) | x) & 0x808080808080ull;
+    const bool dup = (zb & ((1ull << (8u * t)) - 1ull)) != 0;
+    bool ok = live && !dup;
     n_union += ok ? 1u : 0u;
     const uint32_t h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
     ok = ok && (int32_t)h <= tau;
     return ok ? ((h << 16) | (uint32_t)(kid >> 48)) : ~0u;
+}
+
+// Candidate e of the concatenated six bucket runs -> packed key, or ~0u if e
+// is past the runs, outside the epipolar band, a repeat or above tau.
+template <bool EPI>
+__device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, const QueryRuns& r, int32_t tau,
+                                           double dd, uint32_t& n_union) {
+    uint32_t t;
+    const uint32_t pos = entry_pos(e, r, t);
+    bool live = e < r.P6;
+    if constexpr (EPI) live = live && in_band(tv, pos, r, dd);
+    return entry_key(tv, t, pos, live, r, tau, n_union);
 }
 
 // One wavefront per tile of <= 64 consecutive queries of one pair.
@@ -532,7 +554,7 @@ __device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, cons
 //             4 lanes per pair with v_dot4_u32_u8; lane l then takes query l's
 //             distances, picks the nearest and second nearest and applies the
 //             ratio test, and the tile's outputs are stored coalesced.
-template <bool EPI>
+template <bool EPI, int NS>
 __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ imgs,
                                                     const PairDev* __restrict__ pairs,
                                                     const Item* __restrict__ items, int32_t n_items,
@@ -622,10 +644,20 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             qr.qc0 = readlane64(v_qc0, qi);
             qr.qc1 = readlane64(v_qc1, qi);
             qr.qk = readlane64(v_qk, qi);
-            qr.b0 = readlane(v_b[0], qi); qr.b1 = readlane(v_b[1], qi); qr.b2 = readlane(v_b[2], qi);
-            qr.b3 = readlane(v_b[3], qi); qr.b4 = readlane(v_b[4], qi); qr.b5 = readlane(v_b[5], qi);
             qr.P1 = readlane(v_P[0], qi); qr.P2 = readlane(v_P[1], qi); qr.P3 = readlane(v_P[2], qi);
             qr.P4 = readlane(v_P[3], qi); qr.P5 = readlane(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
+            {
+                const uint32_t b0 = readlane(v_b[0], qi), b1 = readlane(v_b[1], qi), b2 = readlane(v_b[2], qi);
+                const uint32_t b3 = readlane(v_b[3], qi), b4 = readlane(v_b[4], qi), b5 = readlane(v_b[5], qi);
+                const uint32_t n = (uint32_t)tv.n;
+                uint32_t cv = b0;
+                cv = lane == 1 ? n + b1 - qr.P1 : cv;
+                cv = lane == 2 ? 2u * n + b2 - qr.P2 : cv;
+                cv = lane == 3 ? 3u * n + b3 - qr.P3 : cv;
+                cv = lane == 4 ? 4u * n + b4 - qr.P4 : cv;
+                cv = lane == 5 ? 5u * n + b5 - qr.P5 : cv;
+                qr.cvec = cv;
+            }
             if constexpr (EPI) {
                 qr.la = readlane_f64(v_la, qi);
                 qr.lb = readlane_f64(v_lb, qi);
@@ -639,21 +671,95 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             // ---- Steps 1-3, gather: union, Hamming, tau, band; index table
             clear_hist(hist, lane);
             uint32_t n_valid = 0;
-            uint32_t kr[4] = {~0u, ~0u, ~0u, ~0u};  // first 256 candidates in registers
-            for (uint32_t base = 0; base < total; base += 256) {
-                uint32_t kv[4];
+            constexpr uint32_t kRegCap = 64u * NS;
+            uint32_t kr[NS];  // candidate keys held in registers (up to kRegCap)
 #pragma unroll
-                for (int u = 0; u < 4; ++u) kv[u] = key_at<EPI>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+            for (int u = 0; u < NS; ++u) kr[u] = ~0u;
+            bool in_regs = true;
+            bool gathered = false;
+            if (total == 0) {
+                gathered = true;  // no candidate: nothing to read (the image may have no entries)
+            } else if constexpr (EPI) {
+                // band first: only keypoints are read for every bucket entry;
+                // the ~1% inside the band are compacted (table, position) into
+                // the LDS list and only they are read in full
+                uint32_t n_surv = 0;
+                for (uint32_t base = 0; base < total; base += 128) {
+                    uint32_t t0, t1;
+                    const uint32_t e0 = base + lane, e1 = base + 64u + lane;
+                    const uint32_t p0 = entry_pos(e0, qr, t0), p1 = entry_pos(e1, qr, t1);
+                    const bool ok0 = e0 < total && in_band(tv, p0, qr, dd);
+                    const bool ok1 = e1 < total && in_band(tv, p1, qr, dd);
+                    const uint64_t m0 = __ballot(ok0);
+                    const uint32_t s0 = n_surv + mbcnt64(m0);
+                    if (ok0 && s0 < (uint32_t)kListCap) list[s0] = (t0 << 24) | p0;
+                    n_surv += (uint32_t)__popcll(m0);
+                    const uint64_t m1 = __ballot(ok1);
+                    const uint32_t s1 = n_surv + mbcnt64(m1);
+                    if (ok1 && s1 < (uint32_t)kListCap) list[s1] = (t1 << 24) | p1;
+                    n_surv += (uint32_t)__popcll(m1);
+                }
+                wave_sync();
+                if (n_surv <= kRegCap && n_surv <= (uint32_t)kListCap) {
+                    const uint32_t slots = (n_surv + 63u) >> 6;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool keep = kv[u] != ~0u;
-                    const uint64_t mk = __ballot(keep);
-                    const uint32_t slot = n_valid + mbcnt64(mk);
-                    if (keep) {
-                        atomicAdd(&hist[kv[u] >> 16], 1u);
-                        if (slot < (uint32_t)kListCap) list[slot] = kv[u];
+                    for (int u = 0; u < NS; ++u) {
+                        if ((uint32_t)u < slots) {
+                            const uint32_t i = 64u * u + lane;
+                            const bool live = i < n_surv;
+                            const uint32_t packed = live ? list[i] : 0u;
+                            kr[u] = entry_key(tv, packed >> 24, live ? (packed & 0xFFFFFFu) : 0u, live, qr, prm.tau,
+                                              st_union);
+                        }
                     }
-                    n_valid += (uint32_t)__popcll(mk);
+#pragma unroll
+                    for (int u = 0; u < NS; ++u) {
+                        const bool keep = kr[u] != ~0u;
+                        if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
+                        n_valid += (uint32_t)__popcll(__ballot(keep));
+                    }
+                    gathered = true;
+                }
+                wave_sync();
+            }
+            if (!gathered) {
+                if (total <= kRegCap) {
+                    // common case: every bucket entry of the query fits the register slots
+#pragma unroll
+                    for (int u = 0; u < NS; ++u) kr[u] = key_at<EPI>(64u * u + lane, tv, qr, prm.tau, dd, st_union);
+#pragma unroll
+                    for (int u = 0; u < NS; ++u) {
+                        const bool keep = kr[u] != ~0u;
+                        if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
+                        n_valid += (uint32_t)__popcll(__ballot(keep));
+                    }
+                } else {
+                    for (uint32_t base = 0; base < total; base += 256) {
+                        uint32_t kv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            kv[u] = key_at<EPI>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const bool keep = kv[u] != ~0u;
+                            const uint64_t mk = __ballot(keep);
+                            const uint32_t slot = n_valid + mbcnt64(mk);
+                            if (keep) {
+                                atomicAdd(&hist[kv[u] >> 16], 1u);
+                                if (slot < (uint32_t)kListCap) list[slot] = kv[u];
+                            }
+                            n_valid += (uint32_t)__popcll(mk);
+                        }
+                    }
+                    in_regs = n_valid <= kRegCap && n_valid <= (uint32_t)kListCap;
+                    wave_sync();
+                    if (in_regs) {
+#pragma unroll
+                        for (int u = 0; u < NS; ++u) {
+                            const uint32_t e = 64u * u + lane;
+                            kr[u] = e < n_valid ? list[e] : ~0u;
+                        }
+                    }
                 }
             }
             wave_sync();
@@ -664,15 +770,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 my_off = sel_n;
             }
             if (kk == 0) continue;
-            const bool in_regs = n_valid <= (uint32_t)kRegCap;
             const bool in_list = n_valid <= (uint32_t)kListCap;
-            if (in_regs) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t e = 64u * u + lane;
-                    kr[u] = e < n_valid ? list[e] : ~0u;
-                }
-            }
             const uint32_t span = in_list ? n_valid : total;
             uint32_t dummy = 0;
             // number of candidate keys in [lo, hi), counted with ballots
@@ -680,7 +778,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     do {                                                                                              \
         c = 0;                                                                                        \
         if (in_regs) {                                                                                \
-            _Pragma("unroll") for (int u = 0; u < 4; ++u) c +=                                        \
+            _Pragma("unroll") for (int u = 0; u < NS; ++u) c +=                                \
                 (uint32_t)__popcll(__ballot(kr[u] >= (lo) && kr[u] < (hi)));                          \
         } else {                                                                                      \
             for (uint32_t base = 0; base < span; base += 64) {                                        \
@@ -707,7 +805,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 uint32_t nt = 0;
                 if (in_regs) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < NS; ++u) {
                         const bool tie = kr[u] >= lo && kr[u] < hi;
                         const uint64_t mk = __ballot(tie);
                         const uint32_t slot = nt + mbcnt64(mk);
@@ -748,7 +846,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             // compaction of the kept candidates into the tile list
             if (in_regs) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < NS; ++u) {
                     const bool keep = kr[u] <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
@@ -921,16 +1019,21 @@ hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const Tabl
     return hipSuccess;
 }
 
-hipError_t launch_match(hipStream_t s, bool epi, int grid, const ImgDev* imgs, const PairDev* pairs, const Item* items,
-                        int32_t n_items, uint32_t* counter, const MatchParams& prm, int32_t* o_idx, int32_t* o_d1,
-                        int32_t* o_d2, unsigned long long* stats) {
+hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev* imgs, const PairDev* pairs,
+                        const Item* items, int32_t n_items, uint32_t* counter, const MatchParams& prm, int32_t* o_idx,
+                        int32_t* o_d1, int32_t* o_d2, unsigned long long* stats) {
     if (n_items <= 0 || grid <= 0) return hipSuccess;
-    if (epi)
-        CH_LAUNCH(match_kernel<true>, dim3(grid), dim3(64 * kWavesPerBlock), 0, s, imgs, pairs, items, n_items,
-                  counter, prm, o_idx, o_d1, o_d2, stats);
+    const dim3 g(grid), b(64 * kWavesPerBlock);
+    if (epi && ns > 4)
+        CH_LAUNCH((match_kernel<true, 8>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats);
+    else if (epi)
+        CH_LAUNCH((match_kernel<true, 4>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats);
+    else if (ns > 4)
+        CH_LAUNCH((match_kernel<false, 8>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2,
+                  stats);
     else
-        CH_LAUNCH(match_kernel<false>, dim3(grid), dim3(64 * kWavesPerBlock), 0, s, imgs, pairs, items, n_items,
-                  counter, prm, o_idx, o_d1, o_d2, stats);
+        CH_LAUNCH((match_kernel<false, 4>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2,
+                  stats);
     return hipSuccess;
 }
 

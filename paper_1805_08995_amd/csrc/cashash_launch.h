@@ -19,7 +19,7 @@ hipError_t launch_fixup(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, 
                         unsigned long long* counter);
 hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const TableOut* touts,
                          const int32_t* train_list, int n_train);
-hipError_t launch_match(hipStream_t s, bool epi, int grid, const ImgDev* imgs, const PairDev* pairs, const Item* items,
+hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev* imgs, const PairDev* pairs, const Item* items,
                         int32_t n_items, uint32_t* counter, const MatchParams& prm, int32_t* o_idx, int32_t* o_d1,
                         int32_t* o_d2, unsigned long long* stats);
 }  // namespace cashash

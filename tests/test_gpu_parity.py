@@ -334,3 +334,36 @@ def test_errors_raise(mats):
     # the context still works after errors
     got, _ = m.match_pairs(dimgs, codes, keys, w.pairs)
     assert got[0].shape[0] == 64
+
+
+# ------------------------------------------------------------------ graph replays
+
+def test_graph_replays_match_eager(mats, monkeypatch):
+    """The batched matcher launch is captured once and replayed; every replay,
+    with unrelated eager work and synchronisations in between, equals the
+    result of a context that never uses graphs."""
+    w = synth.scene_set(seed=13, n_images=6, n_feat=2000, n_scenes=2)
+    monkeypatch.setenv("CASHASH_GRAPHS", "0")
+    eager = binding.Matcher(*mats)
+    monkeypatch.delenv("CASHASH_GRAPHS")
+    graphed = binding.Matcher(*mats)
+    dimgs, codes, keys, _ = _gpu_codes(eager, w.images)
+    ref, st = eager.match_pairs(dimgs, codes, keys, w.pairs)
+    ref = [r.cpu().numpy() for r in ref]
+    assert st["graph_replayed"] == 0
+    out = tuple(torch.full((len(ref[0]),), -7, dtype=torch.int32, device="cuda") for _ in range(3))
+    other = w.pairs[::-1].copy()
+    replays = 0
+    for it in range(5):
+        for o in out:
+            o.fill_(-7)
+        got, st = graphed.match_pairs(dimgs, codes, keys, w.pairs, out=out)
+        replays += st["graph_replayed"]
+        torch.cuda.synchronize()
+        for g, r in zip(got, ref):
+            assert np.array_equal(g.cpu().numpy(), r), f"replay {it}"
+        # eager work between replays: other calls on both contexts
+        eager.match_pairs(dimgs, codes, keys, other)
+        graphed.build_codes(dimgs)
+        torch.cuda.synchronize()
+    assert replays >= 3
