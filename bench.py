@@ -147,13 +147,17 @@ def main():
     n_q = int(sum(nf[q] for q in w.pairs[:, 0]))
     outs = tuple(torch.empty(n_q, dtype=torch.int32, device="cuda") for _ in range(3))
 
+    # code and key buffers, allocated once (each step rewrites them)
+    codes_buf = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for n in nf]
+    keys_buf = [torch.empty((n, 6), dtype=torch.uint8, device="cuda") for n in nf]
+
     def run(m, n_steps, tag):
         st_codes = st_match = None
         kernel_ms, launches = [], 0
         torch.cuda.synchronize()
         t = time.perf_counter()
         for s in range(n_steps):
-            codes, keys, st_codes = m.build_codes(dimgs)
+            codes, keys, st_codes = m.build_codes(dimgs, out=(codes_buf, keys_buf))
             _, st_match = m.match_pairs(dimgs, codes, keys, w.pairs, out=outs)
             ms, launches = m.last_kernel_ms()
             kernel_ms.append(ms)

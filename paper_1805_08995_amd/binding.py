@@ -201,12 +201,16 @@ class Matcher:
             return torch.empty((n, *shape_tail), dtype=tdt, device="cuda")
         return np.zeros((n, *shape_tail), dtype)
 
-    def build_codes(self, images):
+    def build_codes(self, images, out=None):
         """Codes [n,2] (uint64 bits; int64 tensors on the device) and keys [n,6]
-        of every image, centred on the mean of the whole set."""
+        of every image, centred on the mean of the whole set.  out=(codes,
+        keys) reuses caller buffers of those shapes."""
         st, keep = self._images(images)
-        codes = [self._alloc(int(im.shape[0]), (2,), np.uint64) for im in images]
-        keys = [self._alloc(int(im.shape[0]), (6,), np.uint8) for im in images]
+        if out is not None:
+            codes, keys = out
+        else:
+            codes = [self._alloc(int(im.shape[0]), (2,), np.uint64) for im in images]
+            keys = [self._alloc(int(im.shape[0]), (6,), np.uint8) for im in images]
         stats = Stats()
         check(lib().cashash_build_codes(self.h, C.byref(st), self._arrays(codes), self._arrays(keys),
                                         C.byref(stats)))

@@ -541,6 +541,15 @@ __device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, cons
     return entry_key(tv, t, pos, live, r, tau, n_union);
 }
 
+// The first C chunks of 64 candidates into register slots, all loads issued
+// together (slots >= C keep ~0u).
+template <bool EPI, int C, int NS>
+__device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, const TrainView& tv, const QueryRuns& r,
+                                              int32_t tau, double dd, uint32_t& n_union) {
+#pragma unroll
+    for (int u = 0; u < C; ++u) kr[u] = key_at<EPI>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
+}
+
 // One wavefront per tile of <= 64 consecutive queries of one pair.
 //  setup    : lane l loads query l's code, keys and six bucket ranges at once;
 //             each query's values are then broadcast with readlane.
@@ -724,14 +733,33 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             }
             if (!gathered) {
                 if (total <= kRegCap) {
-                    // common case: every bucket entry of the query fits the register slots
-#pragma unroll
-                    for (int u = 0; u < NS; ++u) kr[u] = key_at<EPI>(64u * u + lane, tv, qr, prm.tau, dd, st_union);
+                    // common case: every bucket entry of the query fits the
+                    // register slots; exactly ceil(total / 64) chunks are read
+                    const uint32_t nch = (total + 63u) >> 6;
+                    switch (nch) {
+#define GATHER_CASE(C)                                                                            \
+    case C:                                                                                       \
+        if constexpr (C <= NS) gather_chunks<EPI, C, NS>(kr, lane, tv, qr, prm.tau, dd, st_union); \
+        break;
+                        GATHER_CASE(1)
+                        GATHER_CASE(2)
+                        GATHER_CASE(3)
+                        GATHER_CASE(4)
+                        GATHER_CASE(5)
+                        GATHER_CASE(6)
+                        GATHER_CASE(7)
+                        GATHER_CASE(8)
+#undef GATHER_CASE
+                        default:
+                            break;
+                    }
 #pragma unroll
                     for (int u = 0; u < NS; ++u) {
-                        const bool keep = kr[u] != ~0u;
-                        if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
-                        n_valid += (uint32_t)__popcll(__ballot(keep));
+                        if ((uint32_t)u < nch) {
+                            const bool keep = kr[u] != ~0u;
+                            if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
+                            n_valid += (uint32_t)__popcll(__ballot(keep));
+                        }
                     }
                 } else {
                     for (uint32_t base = 0; base < total; base += 256) {
