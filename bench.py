@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--tau-sweep", action="store_true",
+                    help="also match with Hamming thresholds tau in 128..32 (ranking section) and report matches/time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -212,6 +214,21 @@ def main():
                                          "kernel_ms_per_step": round(float(np.mean(kmsp)), 3)}
         result["speedup_vs_plain"] = round(value / plain_value, 3)
         mp.close()
+    if args.tau_sweep:
+        sweep = []
+        codes, keys, _ = m.build_codes(dimgs, out=(codes_buf, keys_buf))
+        for tau in (128, 64, 56, 48, 40, 32):
+            mt = binding.Matcher(*mats, mode="batched", mem="device", max_hamming=tau)
+            mt.match_pairs(dimgs, codes, keys, w.pairs, out=outs)  # tunes
+            t0 = time.perf_counter()
+            _, stt = mt.match_pairs(dimgs, codes, keys, w.pairs, out=outs)
+            wall = time.perf_counter() - t0
+            kms, _ = mt.last_kernel_ms()
+            sweep.append({"tau": tau, "matches": int((outs[0] >= 0).sum().item()), "kernel_ms": round(kms, 3),
+                          "pairs_per_s": round(n_pairs / wall, 1), "ranked_per_query": round(stt["ranked"] / stt["queries"], 3)})
+            log(f"tau {tau}: {sweep[-1]}")
+            mt.close()
+        result["tau_sweep"] = sweep
     m.close()
     if not args.no_cpu:
         log("cpu baseline: oracle on a bounded sample")

@@ -434,12 +434,12 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     std::vector<RowChunk> tiles;
     int64_t flat = 0;
     for (int m = 0; m < (int)imgs.size(); ++m) {
-        outs[m].flat = flat;
         flat += imgs[m].n;
         for (int r0 = 0; r0 < imgs[m].n; r0 += 16) tiles.push_back({m, r0, std::min(16, imgs[m].n - r0), 0});
     }
     if (tiles.empty()) return CASHASH_OK;
-    RETCHK(c->near.ensure((size_t)flat * 24));
+    // the near list holds at most one entry per descriptor
+    RETCHK(c->near.ensure((size_t)flat * sizeof(NearEntry)));
     Uploader up;
     up.add(imgs);
     up.add(outs);
@@ -451,15 +451,18 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     const RowChunk* dT = (const RowChunk*)d[2];
     const int nt = (int)tiles.size();
     const float coef = (float)c->cfg.margin_coef;
+    unsigned int* near_count = reinterpret_cast<unsigned int*>(c->dCount.as<unsigned long long>() + 1);
+    HIPCHK(launch_fill_u32(c->stream, near_count, 1, 0u));
     if (c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2) {
         const int grid = std::max(1, std::min((nt + 3) / 4, c->n_cu * 8));
         HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
-                                c->near.as<uint64_t>()));
+                                c->near.as<NearEntry>(), near_count));
     } else {
         HIPCHK(launch_proj_fp32(c->stream, dI, dO, dT, nt, c->dR32.as<float>(), c->dBias.as<float>(), coef,
-                                c->near.as<uint64_t>()));
+                                c->near.as<NearEntry>(), near_count));
     }
-    HIPCHK(launch_fixup(c->stream, dI, dO, dT, nt, c->near.as<uint64_t>(), c->dR64.as<double>(),
+    const int fix_grid = (int)std::max<int64_t>(1, std::min<int64_t>((flat + 255) / 256, (int64_t)c->n_cu * 4));
+    HIPCHK(launch_fixup(c->stream, fix_grid, dI, dO, c->near.as<NearEntry>(), near_count, c->dR64.as<double>(),
                         c->dS.as<unsigned long long>(), n_tot, c->dCount.as<unsigned long long>()));
     return CASHASH_OK;
 }
@@ -476,7 +479,7 @@ static int build_codes_device(cashash_ctx* c, const cashash_images* im, uint64_t
         if (n > 0 && (misaligned(im->desc[m], 16) || misaligned(codes_out[m], 8) || misaligned(keys_out[m], 2)))
             return fail(CASHASH_E_INVAL, "image %d: descriptors need 16-byte, codes 8-byte, keys 2-byte alignment", m);
         imgs[m] = ImgDev{im->desc[m], nullptr, nullptr, nullptr, nullptr, nullptr, n, 0};
-        outs[m] = CodeOut{codes_out[m], keys_out[m], 0};
+        outs[m] = CodeOut{codes_out[m], keys_out[m], 0};  // pad
         n_tot += n;
     }
     if (n_tot == 0) {
@@ -517,9 +520,9 @@ struct MatchJob {
 
 static std::vector<Shape> shape_candidates(int k, bool batched) {
     std::vector<Shape> v;
-    const int qmax = std::min(64, kSelCap / k);
+    const int qmax = std::min(kMaxTile, kSelCap / k);
     if (batched) {
-        for (int qt : {16, 32, 64})
+        for (int qt : {8, 16, 32})
             for (int bpc : {4, 6, 8})
                 if (qt <= qmax || qt == 16) v.push_back(Shape{std::min(qt, qmax), bpc});
     } else {
@@ -537,7 +540,7 @@ static std::vector<Shape> shape_candidates(int k, bool batched) {
 }
 
 static Shape default_shape(int k, bool batched) {
-    return batched ? Shape{std::min(64, kSelCap / k), 5} : Shape{std::min(4, kSelCap / k), 0};
+    return batched ? Shape{std::min(kMaxTile, kSelCap / k), 6} : Shape{std::min(4, kSelCap / k), 0};
 }
 
 static bool autotune_enabled() {
@@ -798,7 +801,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     auto hit = c->tuned.find(key);
     const bool tune = hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
     if (hit != c->tuned.end())
-        cands.push_back(Shape{std::min(hit->second.qt, kSelCap / c->cfg.k), hit->second.bpc});
+        cands.push_back(Shape{std::max(1, std::min({hit->second.qt, kMaxTile, kSelCap / c->cfg.k})), hit->second.bpc});
     else if (tune)
         cands = shape_candidates(c->cfg.k, batched);
     else
@@ -1374,3 +1377,4 @@ extern "C" int cashash_match_pairs_epipolar(cashash_ctx* c, const cashash_images
                                             int32_t* d1sq, int32_t* d2sq, cashash_stats* stats) {
     return match_common(c, im, codes, keys, kp_xy, n_pairs, pairs, F, max_px, true, match_idx, d1sq, d2sq, stats);
 }
+

@@ -23,6 +23,7 @@ constexpr int kSelCap = 512;       // per-wave LDS list of a query tile's kept c
 // more resident waves).
 constexpr int kLargeTrain = 9000;
 constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
+constexpr int kMaxTile = 32;       // queries per matcher work item (one per lane of the tile setup)
 
 // Per-image view.  desc/codes/keys/kp are the caller's (or staged) buffers;
 // off/ent are the bucket tables the library builds for train images.
@@ -41,7 +42,15 @@ struct ImgDev {
 struct CodeOut {
     uint64_t* codes;   // [n][2]
     uint8_t* keys;     // [n][6]
-    int64_t flat;      // offset of this image in the flat near-margin mask array
+    int64_t pad;
+};
+
+// A descriptor with at least one projection inside the rounding margin: its
+// image, row and 176-bit mask of the rows to recompute in binary64.
+struct NearEntry {
+    int32_t img;
+    int32_t row;
+    uint64_t mask[3];
 };
 
 // Writable bucket tables of one train image.
@@ -65,7 +74,7 @@ struct PairDev {
     double F[9];        // row-major fundamental matrix (epipolar form)
 };
 
-struct Item {           // a tile of consecutive queries of one pair (nq <= 64, nq * k <= kSelCap)
+struct Item {           // a tile of consecutive queries of one pair (nq <= kMaxTile, nq * k <= kSelCap)
     int32_t pair;
     int32_t q0;
     int32_t nq;

@@ -164,19 +164,35 @@ __device__ __forceinline__ bf16x8 load_frag(const uint4* __restrict__ frag, int 
     return cv.v;
 }
 
-// Writes the fast bits and the near-margin mask of one descriptor.
-__device__ __forceinline__ void store_code(const CodeOut& o, int row, uint64_t w0, uint64_t w1, uint64_t w2,
-                                           uint64_t m0, uint64_t m1, uint64_t m2, uint64_t* __restrict__ near) {
-    o.codes[2 * (int64_t)row] = w0;
-    o.codes[2 * (int64_t)row + 1] = w1;
-    uint16_t* kp = reinterpret_cast<uint16_t*>(o.keys + 6 * (int64_t)row);
-    kp[0] = (uint16_t)(w2 & 0xFFFFu);
-    kp[1] = (uint16_t)((w2 >> 16) & 0xFFFFu);
-    kp[2] = (uint16_t)((w2 >> 32) & 0xFFFFu);
-    uint64_t* nm = near + 3 * (o.flat + row);
-    nm[0] = m0;
-    nm[1] = m1;
-    nm[2] = m2;
+// Writes the fast bits of one descriptor (near-margin bits are 0 until the
+// binary64 recompute) and appends it to the near list if any row is flagged:
+// one atomic per wavefront reserves the wave's slots.
+__device__ __forceinline__ void store_code(const CodeOut& o, int img, int row, bool live, uint64_t w0, uint64_t w1,
+                                           uint64_t w2, uint64_t m0, uint64_t m1, uint64_t m2,
+                                           NearEntry* __restrict__ near, unsigned int* __restrict__ near_count) {
+    if (live) {
+        o.codes[2 * (int64_t)row] = w0;
+        o.codes[2 * (int64_t)row + 1] = w1;
+        uint16_t* kp = reinterpret_cast<uint16_t*>(o.keys + 6 * (int64_t)row);
+        kp[0] = (uint16_t)(w2 & 0xFFFFu);
+        kp[1] = (uint16_t)((w2 >> 16) & 0xFFFFu);
+        kp[2] = (uint16_t)((w2 >> 32) & 0xFFFFu);
+    }
+    const bool flagged = live && (m0 | m1 | m2) != 0;
+    const uint64_t fm = __ballot(flagged);
+    if (fm == 0) return;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == (uint32_t)(__ffsll((unsigned long long)fm) - 1))
+        base = atomicAdd(near_count, (unsigned int)__popcll(fm));
+    base = __builtin_amdgcn_readlane(base, __ffsll((unsigned long long)fm) - 1);
+    if (flagged) {
+        NearEntry& e = near[base + mbcnt64(fm)];
+        e.img = img;
+        e.row = row;
+        e.mask[0] = m0;
+        e.mask[1] = m1;
+        e.mask[2] = m2;
+    }
 }
 
 // BF16 hi+lo split on MFMA.  One wave per tile of 16 descriptors: for each of
@@ -188,7 +204,8 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
                                                         const RowChunk* __restrict__ tiles, int n_tiles,
                                                         const uint4* __restrict__ frag,
                                                         const float* __restrict__ bias, float margin_coef,
-                                                        uint64_t* __restrict__ near) {
+                                                        NearEntry* __restrict__ near,
+                                                        unsigned int* __restrict__ near_count) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int n_waves = (gridDim.x * blockDim.x) >> 6;
@@ -244,7 +261,8 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
             m[k] |= __shfl_xor(m[k], 16);
             m[k] |= __shfl_xor(m[k], 32);
         }
-        if (g == 0 && live) store_code(outs[tc.img], tc.r0 + n, w[0], w[1], w[2], m[0], m[1], m[2], near);
+        store_code(outs[tc.img], tc.img, tc.r0 + n, g == 0 && live, w[0], w[1], w[2], m[0], m[1], m[2], near,
+                   near_count);
     }
 }
 
@@ -255,13 +273,13 @@ __global__ __launch_bounds__(256) void proj_fp32_kernel(const ImgDev* __restrict
                                                         const RowChunk* __restrict__ tiles, int n_tiles,
                                                         const float* __restrict__ R32,
                                                         const float* __restrict__ bias, float margin_coef,
-                                                        uint64_t* __restrict__ near) {
+                                                        NearEntry* __restrict__ near,
+                                                        unsigned int* __restrict__ near_count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int tile = t >> 4, n = t & 15;
-    if (tile >= n_tiles) return;
+    const int tile = min(t >> 4, n_tiles - 1), n = t & 15;
     const RowChunk tc = tiles[tile];
-    if (n >= tc.nr) return;
-    const uint4* xp = reinterpret_cast<const uint4*>(imgs[tc.img].desc + (int64_t)(tc.r0 + n) * kDim);
+    const bool live = (t >> 4) < n_tiles && n < tc.nr;
+    const uint4* xp = reinterpret_cast<const uint4*>(imgs[tc.img].desc + (int64_t)(tc.r0 + (live ? n : 0)) * kDim);
     float xf[kDim];
     uint32_t sq = 0;
 #pragma unroll
@@ -295,56 +313,50 @@ __global__ __launch_bounds__(256) void proj_fp32_kernel(const ImgDev* __restrict
             m[k] |= (uint64_t)nr << rr;
         }
     }
-    store_code(outs[tc.img], tc.r0 + n, w[0], w[1], w[2], m[0], m[1], m[2], near);
+    store_code(outs[tc.img], tc.img, tc.r0 + n, live, w[0], w[1], w[2], m[0], m[1], m[2], near, near_count);
 }
 
 // Binary64 recompute of near-margin projections: the same fused
 // multiply-add chain over components 0..127 of r_j . (N x - S) that defines
 // the codes; N x_i - S_i is an exact integer in binary64.  One thread per
-// descriptor; every thread that recomputes is the only writer of its code.
+// listed descriptor (grid-stride); it is the only writer of that code.
 __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ imgs,
                                                     const CodeOut* __restrict__ outs,
-                                                    const RowChunk* __restrict__ tiles, int n_tiles,
-                                                    const uint64_t* __restrict__ near,
+                                                    const NearEntry* __restrict__ near,
+                                                    const unsigned int* __restrict__ near_count,
                                                     const double* __restrict__ R,
                                                     const unsigned long long* __restrict__ S, double n_tot,
                                                     unsigned long long* __restrict__ counter) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int tile = t >> 4, n = t & 15;
+    const uint32_t n_near = *near_count;
     uint32_t cnt = 0;
-    if (tile < n_tiles) {
-        const RowChunk tc = tiles[tile];
-        if (n < tc.nr) {
-            const CodeOut o = outs[tc.img];
-            const int row = tc.r0 + n;
-            const uint64_t* nm = near + 3 * (o.flat + row);
-            uint64_t mk[3] = {nm[0], nm[1], nm[2]};
-            cnt = __popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]);
-            if (cnt) {
-                const uint8_t* x = imgs[tc.img].desc + (int64_t)row * kDim;
-                uint64_t wd[3] = {o.codes[2 * (int64_t)row], o.codes[2 * (int64_t)row + 1], 0};
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_near; i += gridDim.x * blockDim.x) {
+        const NearEntry e = near[i];
+        const CodeOut o = outs[e.img];
+        const int64_t row = e.row;
+        uint64_t mk[3] = {e.mask[0], e.mask[1], e.mask[2]};
+        cnt += (uint32_t)(__popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]));
+        const uint8_t* x = imgs[e.img].desc + row * kDim;
+        uint64_t wd[3] = {o.codes[2 * row], o.codes[2 * row + 1], 0};
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    while (mk[k]) {
-                        const int bitpos = __ffsll((unsigned long long)mk[k]) - 1;
-                        mk[k] &= mk[k] - 1;
-                        const int r = 64 * k + bitpos;
-                        const double* rr = R + r * kDim;
-                        double p = 0.0;
-                        for (int i = 0; i < kDim; ++i) {
-                            const double c = n_tot * (double)x[i] - (double)S[i];
-                            p = fma(rr[i], c, p);
-                        }
-                        if (p > 0.0) wd[k] |= (uint64_t)1 << bitpos;
-                    }
+        for (int k = 0; k < 3; ++k) {
+            while (mk[k]) {
+                const int bitpos = __ffsll((unsigned long long)mk[k]) - 1;
+                mk[k] &= mk[k] - 1;
+                const int r = 64 * k + bitpos;
+                const double* rr = R + r * kDim;
+                double p = 0.0;
+                for (int i = 0; i < kDim; ++i) {
+                    const double c = n_tot * (double)x[i] - (double)S[i];
+                    p = fma(rr[i], c, p);
                 }
-                o.codes[2 * (int64_t)row] = wd[0];
-                o.codes[2 * (int64_t)row + 1] = wd[1];
-                if (wd[2]) {
-                    uint8_t* kb = o.keys + 6 * (int64_t)row;
-                    for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((wd[2] >> (8 * tb)) & 0xFFu));
-                }
+                if (p > 0.0) wd[k] |= (uint64_t)1 << bitpos;
             }
+        }
+        o.codes[2 * row] = wd[0];
+        o.codes[2 * row + 1] = wd[1];
+        if (wd[2]) {
+            uint8_t* kb = o.keys + 6 * row;
+            for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((wd[2] >> (8 * tb)) & 0xFFu));
         }
     }
     // wave total -> one atomic per wave
@@ -474,7 +486,7 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
 struct QueryRuns {
     uint64_t qc0, qc1, qk;
     uint32_t P1, P2, P3, P4, P5, P6;
-    uint32_t cvec;  // lane u < 6 holds C_u = u * n_t + b_u - P_u: candidate e of table t sits at entry e + C_t
+    const uint32_t* cofs;  // LDS: C_t = t * n_t + b_t - P_t, candidate e of table t sits at entry e + C_t
     double la, lb, lc;
 };
 
@@ -497,7 +509,7 @@ struct TrainView {
 __device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, uint32_t& t) {
     const uint32_t ec = e < r.P6 ? e : 0u;
     t = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
-    return ec + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(t << 2), (int)r.cvec);
+    return ec + r.cofs[t];
 }
 
 // Eq. 1-2: the candidate's keypoint lies within the band around the
@@ -550,7 +562,7 @@ __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, cons
     for (int u = 0; u < C; ++u) kr[u] = key_at<EPI>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
 }
 
-// One wavefront per tile of <= 64 consecutive queries of one pair.
+// One wavefront per tile of <= kMaxTile consecutive queries of one pair.
 //  setup    : lane l loads query l's code, keys and six bucket ranges at once;
 //             each query's values are then broadcast with readlane.
 //  Steps 1-3: per query, the six bucket runs are read four 64-wide chunks at
@@ -574,11 +586,13 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
     __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
+    __shared__ __attribute__((aligned(16))) uint32_t s_cofs[kWavesPerBlock][kMaxTile * 8];  // per query: C_0..C_5
     const int lane = threadIdx.x & 63;
     const int wv = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = s_hist[wv];
     uint32_t* list = s_list[wv];
     uint32_t* sel = s_sel[wv];
+    uint32_t* cofs = s_cofs[wv];
     const int part = lane & 3;
     uint64_t st_bucket = 0, st_ranked = 0;
     uint32_t st_union = 0;
@@ -627,16 +641,24 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
         const uint64_t v_qc0 = gload(Q.codes + 2 * lq), v_qc1 = gload(Q.codes + 2 * lq + 1);
         const uint16_t* kq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * lq);
         const uint64_t v_qk = (uint64_t)gload(kq) | ((uint64_t)gload(kq + 1) << 16) | ((uint64_t)gload(kq + 2) << 32);
-        uint32_t v_b[kTables], v_P[kTables];
+        uint32_t v_P[kTables];
         {
-            uint32_t acc = 0;
+            uint32_t acc = 0, cu[kTables];
 #pragma unroll
             for (int t = 0; t < kTables; ++t) {
                 const uint32_t v = (uint32_t)((v_qk >> (8 * t)) & 0xFFu);
-                v_b[t] = gload(T.off + t * kOffStride + v);
-                acc += gload(T.off + t * kOffStride + v + 1) - v_b[t];
+                const uint32_t b = gload(T.off + t * kOffStride + v);
+                cu[t] = (uint32_t)t * (uint32_t)T.n + b - acc;  // entry of candidate e of table t: e + cu[t]
+                acc += gload(T.off + t * kOffStride + v + 1) - b;
                 v_P[t] = acc;
             }
+            // the previous tile's readers are done (the finalize step ended with a wave sync)
+            if (lane < kMaxTile) {
+                uint4* cw = reinterpret_cast<uint4*>(cofs + 8 * lane);
+                cw[0] = make_uint4(cu[0], cu[1], cu[2], cu[3]);
+                cw[1] = make_uint4(cu[4], cu[5], 0u, 0u);
+            }
+            wave_sync();
         }
         double v_la = 0.0, v_lb = 0.0, v_lc = 0.0;
         if constexpr (EPI) {
@@ -650,23 +672,17 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
 
         for (int qi = 0; qi < nq; ++qi) {
             QueryRuns qr;
-            qr.qc0 = readlane64(v_qc0, qi);
-            qr.qc1 = readlane64(v_qc1, qi);
-            qr.qk = readlane64(v_qk, qi);
+            {
+                // the query's code and keys: wave-uniform addresses, scalar loads
+                const int64_t q = (int64_t)q0 + qi;
+                qr.qc0 = Q.codes[2 * q];
+                qr.qc1 = Q.codes[2 * q + 1];
+                const uint16_t* kqq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * q);
+                qr.qk = (uint64_t)kqq[0] | ((uint64_t)kqq[1] << 16) | ((uint64_t)kqq[2] << 32);
+            }
             qr.P1 = readlane(v_P[0], qi); qr.P2 = readlane(v_P[1], qi); qr.P3 = readlane(v_P[2], qi);
             qr.P4 = readlane(v_P[3], qi); qr.P5 = readlane(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
-            {
-                const uint32_t b0 = readlane(v_b[0], qi), b1 = readlane(v_b[1], qi), b2 = readlane(v_b[2], qi);
-                const uint32_t b3 = readlane(v_b[3], qi), b4 = readlane(v_b[4], qi), b5 = readlane(v_b[5], qi);
-                const uint32_t n = (uint32_t)tv.n;
-                uint32_t cv = b0;
-                cv = lane == 1 ? n + b1 - qr.P1 : cv;
-                cv = lane == 2 ? 2u * n + b2 - qr.P2 : cv;
-                cv = lane == 3 ? 3u * n + b3 - qr.P3 : cv;
-                cv = lane == 4 ? 4u * n + b4 - qr.P4 : cv;
-                cv = lane == 5 ? 5u * n + b5 - qr.P5 : cv;
-                qr.cvec = cv;
-            }
+            qr.cofs = cofs + 8 * qi;
             if constexpr (EPI) {
                 qr.la = readlane_f64(v_la, qi);
                 qr.lb = readlane_f64(v_lb, qi);
@@ -1012,28 +1028,28 @@ hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long*
 }
 
 hipError_t launch_proj_mfma(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
-                            int n_tiles, const uint4* frag, const float* bias, float margin, uint64_t* near) {
+                            int n_tiles, const uint4* frag, const float* bias, float margin, NearEntry* near,
+                            unsigned int* near_count) {
     if (n_tiles <= 0) return hipSuccess;
-    CH_LAUNCH(proj_mfma_kernel, dim3(grid), dim3(256), 0, s, imgs, outs, tiles, n_tiles, frag, bias, margin, near);
+    CH_LAUNCH(proj_mfma_kernel, dim3(grid), dim3(256), 0, s, imgs, outs, tiles, n_tiles, frag, bias, margin, near,
+              near_count);
     return hipSuccess;
 }
 
 hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
-                            int n_tiles, const float* R32, const float* bias, float margin, uint64_t* near) {
+                            int n_tiles, const float* R32, const float* bias, float margin, NearEntry* near,
+                            unsigned int* near_count) {
     if (n_tiles <= 0) return hipSuccess;
     const int64_t threads = (int64_t)n_tiles * 16;
     CH_LAUNCH(proj_fp32_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, imgs, outs, tiles, n_tiles,
-              R32, bias, margin, near);
+              R32, bias, margin, near, near_count);
     return hipSuccess;
 }
 
-hipError_t launch_fixup(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles, int n_tiles,
-                        const uint64_t* near, const double* R, const unsigned long long* S, double n_tot,
+hipError_t launch_fixup(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+                        const unsigned int* near_count, const double* R, const unsigned long long* S, double n_tot,
                         unsigned long long* counter) {
-    if (n_tiles <= 0) return hipSuccess;
-    const int64_t threads = (int64_t)n_tiles * 16;
-    CH_LAUNCH(fixup_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, imgs, outs, tiles, n_tiles, near,
-              R, S, n_tot, counter);
+    CH_LAUNCH(fixup_kernel, dim3(grid), dim3(256), 0, s, imgs, outs, near, near_count, R, S, n_tot, counter);
     return hipSuccess;
 }
 

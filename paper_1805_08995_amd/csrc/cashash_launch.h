@@ -11,11 +11,13 @@ hipError_t launch_colsum(hipStream_t s, const ImgDev* imgs, const RowChunk* chun
                          unsigned long long* S);
 hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long* S, double n_tot, float* bias);
 hipError_t launch_proj_mfma(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
-                            int n_tiles, const uint4* frag, const float* bias, float margin, uint64_t* near);
+                            int n_tiles, const uint4* frag, const float* bias, float margin, NearEntry* near,
+                            unsigned int* near_count);
 hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
-                            int n_tiles, const float* R32, const float* bias, float margin, uint64_t* near);
-hipError_t launch_fixup(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles, int n_tiles,
-                        const uint64_t* near, const double* R, const unsigned long long* S, double n_tot,
+                            int n_tiles, const float* R32, const float* bias, float margin, NearEntry* near,
+                            unsigned int* near_count);
+hipError_t launch_fixup(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+                        const unsigned int* near_count, const double* R, const unsigned long long* S, double n_tot,
                         unsigned long long* counter);
 hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const TableOut* touts,
                          const int32_t* train_list, int n_train);
@@ -23,3 +25,4 @@ hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev*
                         int32_t n_items, uint32_t* counter, const MatchParams& prm, int32_t* o_idx, int32_t* o_d1,
                         int32_t* o_d2, unsigned long long* stats);
 }  // namespace cashash
+

@@ -367,3 +367,29 @@ def test_graph_replays_match_eager(mats, monkeypatch):
         graphed.build_codes(dimgs)
         torch.cuda.synchronize()
     assert replays >= 3
+
+
+def test_autotune_cache_file_and_fixed_shape(mats, monkeypatch, tmp_path):
+    """The autotuner writes its choice as a JSON line to CASHASH_AUTOTUNE_CACHE
+    and a new context reuses it; CASHASH_AUTOTUNE=0 uses the fixed default.
+    Every launch shape gives the same outputs."""
+    import json
+    w = synth.scene_set(seed=14, n_images=4, n_feat=1500, n_scenes=2)
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("CASHASH_AUTOTUNE_CACHE", str(cache))
+    m1 = binding.Matcher(*mats)
+    dimgs, codes, keys, _ = _gpu_codes(m1, w.images)
+    ref, st1 = m1.match_pairs(dimgs, codes, keys, w.pairs)
+    ref = [r.cpu().numpy() for r in ref]
+    lines = [json.loads(x) for x in cache.read_text().splitlines()]
+    assert len(lines) == 1 and lines[0]["qt"] == st1["tile_queries"] and lines[0]["key"].startswith("gfx950/batched")
+    m2 = binding.Matcher(*mats)
+    got, st2 = m2.match_pairs(dimgs, codes, keys, w.pairs)
+    assert (st2["tile_queries"], st2["blocks_per_cu"]) == (st1["tile_queries"], st1["blocks_per_cu"])
+    assert len(cache.read_text().splitlines()) == 1  # reused, not tuned again
+    monkeypatch.delenv("CASHASH_AUTOTUNE_CACHE")
+    monkeypatch.setenv("CASHASH_AUTOTUNE", "0")
+    m3 = binding.Matcher(*mats)
+    got3, st3 = m3.match_pairs(dimgs, codes, keys, w.pairs)
+    for a, b, c in zip(ref, got, got3):
+        assert np.array_equal(a, b.cpu().numpy()) and np.array_equal(a, c.cpu().numpy())

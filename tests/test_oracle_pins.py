@@ -383,3 +383,33 @@ def test_match_pairs_equals_per_pair(orc):
     full = orc.match_pair(w.images[0], codes[0], keys[0], w.images[1], codes[1], keys[1], k=10)
     for a, b in zip(sub, full):
         assert np.array_equal(a, b[sel])
+
+
+def test_tau_invariant_when_k_candidates_survive(orc):
+    """Ranking section: dropping candidates with Hamming distance > tau cannot
+    change a query whose k nearest (Hamming, index) candidates all have
+    distance <= tau; checked per query against a Python count of the union."""
+    rc, rb = synth.projection_matrices()
+    w = synth.single_pair(n=1200, n_shared=700)
+    codes, keys = orc.build_codes(w.images, rc, rb)
+    A, B = w.images
+    full = orc.match_pair(A, codes[0], keys[0], B, codes[1], keys[1], k=10)
+    k = 10
+    total_checked = 0
+    for tau in (56, 60, 64):
+        cut = orc.match_pair(A, codes[0], keys[0], B, codes[1], keys[1], k=k, tau=tau)
+        cb = [int(c0) | (int(c1) << 64) for c0, c1 in codes[1]]
+        n_same = n_checked = 0
+        for q in range(0, len(A), 7):
+            cq = int(codes[0][q, 0]) | (int(codes[0][q, 1]) << 64)
+            union = {j for t in range(6) for j in np.flatnonzero(keys[1][:, t] == keys[0][q, t])}
+            hs = sorted((cq ^ cb[j]).bit_count() for j in union)
+            if len(hs) >= k and hs[k - 1] <= tau:
+                n_checked += 1
+                assert (full[0][q], full[1][q], full[2][q]) == (cut[0][q], cut[1][q], cut[2][q])
+            n_same += int(full[0][q] == cut[0][q])
+        total_checked += n_checked
+    assert total_checked > 50
+    # a tau below every Hamming distance of a true match loses matches
+    low = orc.match_pair(A, codes[0], keys[0], B, codes[1], keys[1], k=k, tau=2)
+    assert (low[0] >= 0).sum() < (full[0] >= 0).sum()
