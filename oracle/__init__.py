@@ -13,6 +13,7 @@ Parity status per function (what pins each one is in tests/test_oracle_pins.py):
                                         order, golden worked example)
   epipolar band                      -- pinned (rectified-stereo closed form,
                                         huge band equals plain matching)
+  geometry (oracle.geometry)         -- pinned (see geometry_oracle.c)
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cashash_oracle.c")
+_SRC_GEO = os.path.join(_HERE, "geometry_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libcashash_oracle.so")
 DIM, TABLES = 128, 6
 
@@ -33,7 +35,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fopenmp",
-                        "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"], check=True)
+                        "-shared", "-fPIC", "-o", tmp, _SRC, _SRC_GEO, "-lm"], check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -49,7 +51,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_GEO)):
             build()
         L = C.CDLL(LIB_PATH)
         P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double

@@ -65,6 +65,7 @@ class Workload:
     kp: optional list of float32 [n_i, 2] keypoints (epipolar form).
     F: optional float64 [P, 9] row-major fundamental matrices; the epipolar
         line of query point (x, y) in the train image is F @ (x, y, 1).
+    scales: optional list of float32 [n_i] feature scales.
     """
     name: str
     images: list
@@ -73,6 +74,7 @@ class Workload:
     kp: list | None = None
     F: np.ndarray | None = None
     max_px: float = 4.0
+    scales: list | None = None
 
     @property
     def n_feat(self) -> np.ndarray:
@@ -180,26 +182,15 @@ def _skew(t: np.ndarray) -> np.ndarray:
     return np.array([[0.0, -t[2], t[1]], [t[2], 0.0, -t[0]], [-t[1], t[0], 0.0]])
 
 
-def epipolar_set(seed: int = 5, n_images: int = 500, n_feat: int = 12000,
-                 n_points: int = 200_000, n_neighbours: int = 30,
-                 radius: float = 40.0, half_cube: float = 10.0,
-                 focal: float = 1500.0, width: int = 1920, height: int = 1080,
-                 kp_sigma: float = 0.5, max_px: float = 4.0) -> Workload:
-    """Pinhole cameras on a horizontal circle around a cube of random 3-D
-    points.  Each image observes n_feat distinct points that project inside
-    the frame; keypoint = projection + N(0, kp_sigma^2) px (float32);
-    descriptor = noisy copy of the point's base descriptor.  Each camera is
-    paired with its n_neighbours nearest cameras on the orbit; F is the true
-    fundamental matrix of the (query, train) pair."""
-    rng = np.random.default_rng(seed)
-    pts = rng.uniform(-half_cube, half_cube, (n_points, 3))
-    base = desc(rng, n_points)
-    K = np.array([[focal, 0.0, width / 2], [0.0, focal, height / 2], [0.0, 0.0, 1.0]])
-    Kinv = np.linalg.inv(K)
-    Rs, ts = [], []
-    images, truth, kps = [], [], []
+def _orbit_images(rng, pts, base, n_images, n_feat, radius, K, width, height, kp_sigma, phase=0.0):
+    """Cameras on a horizontal circle of the given radius, looking at the
+    origin.  Image i observes n_feat random points that project inside the
+    frame: keypoint = projection + N(0, kp_sigma^2) px (float32), descriptor
+    = noisy copy of the point's base descriptor.  Returns per-image lists of
+    descriptors, point ids, keypoints and depths, and the cameras (R, t)."""
+    Rs, ts, images, truth, kps, depths = [], [], [], [], [], []
     for i in range(n_images):
-        th = 2.0 * math.pi * i / n_images
+        th = 2.0 * math.pi * i / n_images + phase
         c = np.array([radius * math.cos(th), radius * math.sin(th), 0.0])
         R = _look_at(c)
         t = -R @ c
@@ -215,23 +206,96 @@ def epipolar_set(seed: int = 5, n_images: int = 500, n_feat: int = 12000,
         images.append(noisy(rng, base[sel]))
         truth.append(sel.astype(np.int64))
         kps.append(np.ascontiguousarray(kp))
+        depths.append(cam[sel, 2])
+    return images, truth, kps, depths, Rs, ts
+
+
+def _intrinsics(focal, width, height):
+    return np.array([[focal, 0.0, width / 2], [0.0, focal, height / 2], [0.0, 0.0, 1.0]])
+
+
+def _true_F(K, Ri, ti, Rj, tj):
+    """Fundamental matrix of (query camera i, train camera j):
+    F = K^-T [t]x R K^-1 with R = Rj Ri^T, t = tj - R ti."""
+    Kinv = np.linalg.inv(K)
+    R = Rj @ Ri.T
+    t = tj - R @ ti
+    return (Kinv.T @ _skew(t) @ R @ Kinv).reshape(9)
+
+
+def epipolar_set(seed: int = 5, n_images: int = 500, n_feat: int = 12000,
+                 n_points: int = 200_000, n_neighbours: int = 30,
+                 radius: float = 40.0, half_cube: float = 10.0,
+                 focal: float = 1500.0, width: int = 1920, height: int = 1080,
+                 kp_sigma: float = 0.5, max_px: float = 4.0) -> Workload:
+    """Pinhole cameras on a horizontal circle around a cube of random 3-D
+    points.  Each image observes n_feat distinct points that project inside
+    the frame; keypoint = projection + N(0, kp_sigma^2) px (float32);
+    descriptor = noisy copy of the point's base descriptor.  Each camera is
+    paired with its n_neighbours nearest cameras on the orbit; F is the true
+    fundamental matrix of the (query, train) pair."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(-half_cube, half_cube, (n_points, 3))
+    base = desc(rng, n_points)
+    K = _intrinsics(focal, width, height)
+    images, truth, kps, _, Rs, ts = _orbit_images(rng, pts, base, n_images, n_feat, radius, K, width, height,
+                                                  kp_sigma)
     half = n_neighbours // 2
     pairs, Fs = [], []
     for i in range(n_images):
         for off in list(range(-half, 0)) + list(range(1, n_neighbours - half + 1)):
             j = (i + off) % n_images
-            R = Rs[j] @ Rs[i].T
-            t = ts[j] - R @ ts[i]
-            F = Kinv.T @ _skew(t) @ R @ Kinv
             pairs.append((i, j))
-            Fs.append(F.reshape(9))
+            Fs.append(_true_F(K, Rs[i], ts[i], Rs[j], ts[j]))
     return Workload(f"epipolar_{n_images}x{n_feat}", images, np.array(pairs, np.int32), truth,
                     kp=kps, F=np.ascontiguousarray(np.array(Fs, np.float64)), max_px=max_px)
 
 
-WORKLOADS = {
-    "single_pair": single_pair,
-    "scenes": scene_set,
-    "uneven": uneven_set,
-    "epipolar": epipolar_set,
-}
+def geometric_set(seed: int = 6, n_scenes: int = 2, cams_per_scene: int = 250, n_feat: int = 12000,
+                  n_points: int = 200_000, n_near: int = 20, n_far: int = 10,
+                  radius: float = 40.0, half_cube: float = 10.0,
+                  focal: float = 1500.0, width: int = 1920, height: int = 1080,
+                  kp_sigma: float = 0.5, max_px: float = 4.0,
+                  size_median: float = 0.04, size_sigma: float = 0.6, scale_jitter: float = 0.1) -> Workload:
+    """Inputs of two-stage geometry-aware matching: n_scenes independent
+    scenes (own 3-D points, own descriptor pool), each seen by an orbit of
+    cams_per_scene cameras as in epipolar_set.  Every 3-D point has a
+    physical size (log-normal); a feature's scale is focal * size / depth
+    times a log-normal jitter, so the largest-scale features of neighbouring
+    views are largely the same points.  Each camera is paired with its n_near
+    nearest cameras of its own orbit and n_far random cameras of other scenes
+    (pairs with no common point).  F holds the true fundamental matrix of
+    same-scene pairs and zeros for the others (not an input of the method)."""
+    rng = np.random.default_rng(seed)
+    K = _intrinsics(focal, width, height)
+    images, truth, kps, scales, cams, scene_of = [], [], [], [], [], []
+    for sc in range(n_scenes):
+        pts = rng.uniform(-half_cube, half_cube, (n_points, 3))
+        base = desc(rng, n_points)
+        size = np.exp(rng.standard_normal(n_points) * size_sigma) * size_median
+        im, tr, kp, dep, Rs, ts = _orbit_images(rng, pts, base, cams_per_scene, n_feat, radius, K, width, height,
+                                                kp_sigma, phase=0.37 * sc)
+        for i in range(cams_per_scene):
+            jit = np.exp(rng.standard_normal(len(tr[i])) * scale_jitter)
+            scales.append(np.ascontiguousarray((focal * size[tr[i]] / dep[i] * jit).astype(np.float32)))
+            cams.append((Rs[i], ts[i]))
+            scene_of.append(sc)
+        images += im
+        truth += [t + sc * n_points for t in tr]
+        kps += kp
+    n_images = len(images)
+    scene_of = np.array(scene_of)
+    half = n_near // 2
+    pairs, Fs = [], []
+    for i in range(n_images):
+        sc, a = divmod(i, cams_per_scene)
+        for off in list(range(-half, 0)) + list(range(1, n_near - half + 1)):
+            j = sc * cams_per_scene + (a + off) % cams_per_scene
+            pairs.append((i, j))
+            Fs.append(_true_F(K, cams[i][0], cams[i][1], cams[j][0], cams[j][1]))
+        others = np.flatnonzero(scene_of != sc)
+        for j in rng.choice(others, size=min(n_far, len(others)), replace=False):
+            pairs.append((i, int(j)))
+            Fs.append(np.zeros(9))
+    return Workload(f"geometric_{n_images}x{n_feat}", images, np.array(pairs, np.int32), truth,
+                    kp=kps, F=np.ascontiguousarray(np.array(Fs, np.float64)), max_px=max_px, scales=scales)
