@@ -9,6 +9,12 @@ before timing; outputs stay in HBM.  Prints ONE JSON line on stdout;
 progress goes to stderr.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-plain]
+                  [--tau-sweep] [--geometric]
+
+--geometric adds the two-stage geometry-aware form (top-scale subset
+matching, RANSAC fundamental matrices, guided matching of accepted pairs) on
+2 scenes x 250 cameras x 12000 features with 15000 pairs, against unguided
+matching of the same pairs.
 """
 from __future__ import annotations
 
@@ -27,19 +33,25 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes of one full matcher launch on this workload, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy (x2.0 and x1.0); see
-# profiles/match_kernel_scenes_100x8000.md.  Valid only for the kernel source
-# they were taken on.
-MEASURED_TRAFFIC = {"kernels_sha256": "80d70e1babf4d2c76169d68ce8e6aa1bf2ce0bf60b5d85e799475c79e2a00d5c",
+# profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
+# sources they were taken on (sha256 over MATCHER_SOURCES, in order).
+MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
+MEASURED_TRAFFIC = {"sources_sha256": None,
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": 4381058 * 1024 * 2, "write_bytes": 479123 * 1024}
+                    "fetch_bytes": 0, "write_bytes": 0}
+
+
+def matcher_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in MATCHER_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1805_08995_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
-    import hashlib
-    src = os.path.join(ROOT, "paper_1805_08995_amd", "csrc", "cashash_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     t = MEASURED_TRAFFIC
-    if sha != t["kernels_sha256"] or workload != t["workload"]:
+    if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
 
@@ -100,6 +112,85 @@ def cpu_baseline(w, mats, budget_s=20.0):
                        f"{step_s:.1f}s")}
 
 
+def geometric_leg(binding, synth, torch, steps, cpu_seconds, no_cpu):
+    """Two-stage geometry-aware matching vs unguided matching of the same
+    pairs; the oracle's fundamental-matrix step timed on a sample of pairs
+    whose stage-1 matches it computes itself."""
+    from oracle import geometry as G
+    import oracle
+    log("geometric: generating 2 scenes x 250 cameras x 12000 features, 15000 pairs")
+    w = synth.geometric_set()
+    mats = synth.projection_matrices()
+
+    def dev(arrs):
+        flat = torch.from_numpy(np.concatenate(arrs)).cuda()
+        offs = np.concatenate([[0], np.cumsum([len(a) for a in arrs])])
+        return [flat[offs[i]:offs[i + 1]] for i in range(len(arrs))]
+
+    d, kp, sc = dev(w.images), dev(w.kp), dev(w.scales)
+    rand = np.random.default_rng(7).integers(0, 2**32, (256, 8), dtype=np.uint64).astype(np.uint32)
+    m = binding.Matcher(*mats, mode="batched", mem="device")
+    codes, keys, _ = m.build_codes(d)
+    n_q = int(sum(w.images[q].shape[0] for q in w.pairs[:, 0]))
+    outs = tuple(torch.empty(n_q, dtype=torch.int32, device="cuda") for _ in range(3))
+    P = len(w.pairs)
+    m.match_pairs_geometric(d, codes, keys, kp, sc, w.pairs, rand, out=outs)      # tunes both stages
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, res, st = m.match_pairs_geometric(d, codes, keys, kp, sc, w.pairs, rand, out=outs)
+    torch.cuda.synchronize()
+    dt_geo = (time.perf_counter() - t0) / steps
+    stage_ms = m.last_geometric_ms()
+    matches_geo = int((outs[0] >= 0).sum().item())
+    m.match_pairs(d, codes, keys, w.pairs, out=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.match_pairs(d, codes, keys, w.pairs, out=outs)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t0) / steps
+    matches_plain = int((outs[0] >= 0).sum().item())
+    acc = int((res["status"] == 0).sum())
+    out = {"workload": f"geometric_2x250x12000_{P}pairs", "pairs": P, "accepted": acc,
+           "status_counts": [int((res["status"] == s).sum()) for s in range(4)],
+           "two_stage_pairs_per_s": round(P / dt_geo, 1), "unguided_pairs_per_s": round(P / dt_plain, 1),
+           "speedup_vs_unguided": round(dt_plain / dt_geo, 3),
+           "stage_ms": {"subset_gather": round(stage_ms[0], 3), "stage1": round(stage_ms[1], 3),
+                        "fundamental": round(stage_ms[2], 3), "stage2": round(stage_ms[3], 3)},
+           "matches_two_stage": matches_geo, "matches_unguided": matches_plain,
+           "fundamental_us_per_pair_gpu": round(stage_ms[2] * 1e3 / P, 3)}
+    log(f"geometric: {out}")
+    if not no_cpu:
+        # oracle fundamental step on pairs whose stage-1 matches the oracle computes
+        S, N = oracle.column_sums(w.images)
+        rng = np.random.default_rng(1)
+        sample = rng.choice(P, size=min(P, 300), replace=False)
+        imgs = sorted(set(w.pairs[sample].ravel().tolist()))
+        rows = {i: G.top_scale(w.scales[i]) for i in imgs}
+        sub = {i: w.images[i][rows[i]] for i in imgs}
+        ck = {i: oracle.project(sub[i], S, N, *mats) for i in imgs}
+        ql, tl = [], []
+        for p in sample:
+            qi, ti = (int(x) for x in w.pairs[p])
+            mi = oracle.match_pair(sub[qi], *ck[qi], sub[ti], *ck[ti], k=10)[0]
+            a, b = G.stage1_points(w.kp[qi][rows[qi]], w.kp[ti][rows[ti]], mi)
+            ql.append(a)
+            tl.append(b)
+        reps, t_f = 0, 0.0
+        while t_f < min(cpu_seconds, 10.0) or reps == 0:
+            t0 = time.perf_counter()
+            G.fundamental_batch(ql, tl, rand)
+            t_f += time.perf_counter() - t0
+            reps += 1
+        us = t_f / reps / len(sample) * 1e6
+        out["oracle_fundamental_us_per_pair"] = round(us, 2)
+        out["oracle_cores"] = oracle.num_threads()
+        out["fundamental_speedup_vs_oracle"] = round(us / max(out["fundamental_us_per_pair_gpu"], 1e-9), 1)
+    m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +203,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tau-sweep", action="store_true",
                     help="also match with Hamming thresholds tau in 128..32 (ranking section) and report matches/time")
+    ap.add_argument("--geometric", action="store_true",
+                    help="also run the two-stage geometry-aware form on 2 scenes x 250 cameras x 12000 features")
+    ap.add_argument("--geometric-only", action="store_true",
+                    help="run only the two-stage form (for profiling) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -134,6 +229,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "dispatches": 3}), flush=True)
         return
     binding.lib()
+    if args.geometric_only:
+        print(json.dumps(geometric_leg(binding, synth, torch, args.steps, args.cpu_seconds, args.no_cpu)), flush=True)
+        return
 
     log(f"generating {args.images} images x {args.feats} features")
     t0 = time.perf_counter()
@@ -230,6 +328,8 @@ def main():
             mt.close()
         result["tau_sweep"] = sweep
     m.close()
+    if args.geometric:
+        result["geometric"] = geometric_leg(binding, synth, torch, args.steps, args.cpu_seconds, args.no_cpu)
     if not args.no_cpu:
         log("cpu baseline: oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(w, mats, args.cpu_seconds)

@@ -182,6 +182,116 @@ int cashash_plan_schedule(int32_t n_images, const int64_t* img_bytes, int64_t n_
  * number of launches it covered. */
 int cashash_last_kernel_ms(cashash_ctx* ctx, double* ms, int64_t* launches);
 
+/* ---- Geometry-aware two-stage matching ("Image Matching with Geometry-aware
+ * Cascade Hashing on GPU", first stage and guided second stage) -----------
+ *
+ * Stage 1 matches the largest-scale fraction (default one fifth) of every
+ * image's features over the given pairs; a pair with at least min_matches
+ * stage-1 matches gets a fundamental matrix estimated from them and is
+ * accepted iff at least two thirds of its matches are inliers of that
+ * matrix; stage 2 matches all features of the accepted pairs with the
+ * epipolar band of Eq. 1-2 around the estimated matrix.  The paper leaves
+ * the estimator open; this library uses RANSAC over Hartley-normalised
+ * eight-point hypotheses with a least-squares refit on the best hypothesis's
+ * inliers, in binary64 with every sum taken sequentially in match order:
+ *   - hypothesis h draws 8 distinct match indices by Floyd's algorithm from
+ *     rand8[h][0..7]: for j = n-8 .. n-1, v = floor(r (j+1) / 2^32), and j
+ *     instead if v was already drawn;
+ *   - its matrix is the null vector (f8 = 1) of the 8 x 9 design matrix
+ *     [u x, u y, u, v x, v y, v, x, y, 1] of the normalised sample (Gaussian
+ *     elimination, partial pivoting), made rank 2 by removing the component
+ *     along the eigenvector of F^T F with the smallest eigenvalue (cyclic
+ *     Jacobi, 6 sweeps), mapped back to pixels (F = T_t^T F T_q);
+ *   - a match is an inlier iff its train point lies within thr_px of the
+ *     query point's epipolar line, tested exactly as the band of
+ *     cashash_match_pairs_epipolar;
+ *   - the best hypothesis has the most inliers (lowest index on ties); the
+ *     refit takes the smallest eigenvector of A^T A over its inliers (cyclic
+ *     Jacobi, 10 sweeps), rank 2, pixels, and counts inliers again.
+ * These calls need cfg.mem == CASHASH_MEM_DEVICE (else E_INVAL); per-image
+ * arrays hold device pointers, per-pair results are host arrays. */
+
+#define CASHASH_GEO_ACCEPT 0        /* guided matching runs for the pair */
+#define CASHASH_GEO_FEW_MATCHES 1   /* fewer than max(min_matches, 8) stage-1 matches */
+#define CASHASH_GEO_DEGENERATE 2    /* coincident points or no hypothesis with >= 8 inliers */
+#define CASHASH_GEO_FEW_INLIERS 3   /* 3 * inliers < 2 * matches after the refit */
+#define CASHASH_GEO_MAX_MATCHES 8192 /* query points per image in cashash_estimate_fundamental */
+
+typedef struct {
+    int32_t frac_num, frac_den; /* stage-1 subset: ceil(n frac_num / frac_den) features (default 1 / 5) */
+    int32_t min_matches;        /* default 16 */
+    int32_t n_hyp;              /* RANSAC hypotheses, 1..2^20 (default 256) */
+    double ransac_px;           /* inlier distance to the epipolar line, px (default 2.0) */
+    double band_px;             /* stage-2 band half-width d of Eq. 1 (default 4.0) */
+    const uint32_t* rand8;      /* host uint32 [n_hyp][8] uniform draws (required; default NULL) */
+} cashash_geometric_config;
+
+/* Fill g with the defaults above. */
+void cashash_default_geometric_config(cashash_geometric_config* g);
+
+/* ceil(n frac_num / frac_den), or -1 unless n >= 0 and 0 < frac_num <= frac_den.
+ * Host only. */
+int64_t cashash_subset_size(int32_t n, int32_t frac_num, int32_t frac_den);
+
+/* Stage-1 subset of each image: rows_out[m] (device int32
+ * [cashash_subset_size(n_feat[m], ..)]) receives the indices of the largest
+ * scales[m] values (device float32 [n_feat[m]]), ordered by the IEEE-754
+ * total order (so -0 < +0; NaN with the sign bit clear ranks above +inf),
+ * lower index first on ties, written in ascending index order.
+ * Errors: E_INVAL (host mode, null or misaligned pointer, bad fraction),
+ * E_LIMIT (n_feat > 65535), E_DEVICE. */
+int cashash_select_top_scale(cashash_ctx* ctx, int32_t n_images, const float* const* scales, const int32_t* n_feat,
+                             int32_t frac_num, int32_t frac_den, int32_t* const* rows_out);
+
+/* Row gather per image m: out row j = input row rows[m][j], j < n_rows[m],
+ * for each field whose input and output arrays are both given (desc 128 B,
+ * codes 2 x uint64, keys 6 B, kp 2 x float32; pass NULL for both to skip a
+ * field).  All pointers inside the arrays are device pointers; alignment as
+ * for matching (desc 16, codes 8, keys 2, kp 4 bytes).
+ * Errors: E_INVAL (host mode, null or misaligned buffer, a row outside
+ * 0..n_feat[m]-1; the other rows are copied), E_DEVICE. */
+int cashash_gather_rows(cashash_ctx* ctx, int32_t n_images, const int32_t* n_feat, const int32_t* n_rows,
+                        const int32_t* const* rows, const uint8_t* const* desc, const uint64_t* const* codes,
+                        const uint8_t* const* keys, const float* const* kp, uint8_t* const* desc_out,
+                        uint64_t* const* codes_out, uint8_t* const* keys_out, float* const* kp_out);
+
+/* Fundamental matrix of each pair from its matches.  match_idx: device, the
+ * flat match_idx output of cashash_match_pairs for the same n_feat and pairs
+ * (pair p's slots follow those of the pairs before it; a slot >= 0 is a
+ * match of that query point).  kp_xy[m]: device float32 [n_feat[m]][2].
+ * Matches are taken in ascending query order.  Outputs, host [n_pairs]:
+ * F_out [n_pairs][9] row-major (zeros unless a refit ran), n_matches,
+ * n_inliers (of the refit matrix), best_hyp (the best hypothesis, -1 if
+ * none was solvable or none ran; may be NULL) and status (CASHASH_GEO_*).
+ * Errors: E_INVAL (host mode, null pointer, pair out of range, bad n_hyp or
+ * threshold, a match index outside its train image), E_LIMIT (a query
+ * image with more than CASHASH_GEO_MAX_MATCHES points), E_DEVICE. */
+int cashash_estimate_fundamental(cashash_ctx* ctx, int32_t n_images, const int32_t* n_feat,
+                                 const float* const* kp_xy, int64_t n_pairs, const int32_t* pairs,
+                                 const int32_t* match_idx, const uint32_t* rand8, int32_t n_hyp, double thr_px,
+                                 int32_t min_matches, double* F_out, int32_t* n_matches, int32_t* n_inliers,
+                                 int32_t* best_hyp, int32_t* status);
+
+/* The two stages over device-resident images: subset selection, row gather
+ * and stage-1 matching into library-owned device memory, fundamental
+ * matrices, then cashash_match_pairs_epipolar (band g->band_px) over the
+ * accepted pairs.  Outputs: per pair (host) F_out [n_pairs][9], n_matches,
+ * n_inliers, status as cashash_estimate_fundamental; per query (device) the
+ * flat layout of cashash_match_pairs over ALL pairs, with every slot of a
+ * pair that was not accepted set to -1.  stats: those of stage 2, with pairs
+ * and queries counted over all pairs and ms_match the whole call.
+ * Errors: as the calls it is made of. */
+int cashash_match_pairs_geometric(cashash_ctx* ctx, const cashash_images* images, const uint64_t* const* codes,
+                                  const uint8_t* const* keys, const float* const* kp_xy, const float* const* scales,
+                                  int64_t n_pairs, const int32_t* pairs, const cashash_geometric_config* g,
+                                  double* F_out, int32_t* n_matches, int32_t* n_inliers, int32_t* status,
+                                  int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats);
+
+/* Device time of the last cashash_match_pairs_geometric call's four parts,
+ * in milliseconds (HIP events on its stream): subset selection and gather,
+ * stage-1 matching, fundamental matrices, stage 2 (fills included). */
+int cashash_last_geometric_ms(cashash_ctx* ctx, double* ms4);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,12 @@ MODES = {"batched": MODE_BATCHED_BF16X2, "plain": MODE_PLAIN_FP32_PER_PAIR}
 MEMS = {"host": MEM_HOST, "device": MEM_DEVICE}
 EXPORTED = ["cashash_default_config", "cashash_create", "cashash_set_config", "cashash_destroy",
             "cashash_build_codes", "cashash_match_pairs", "cashash_match_pairs_epipolar",
-            "cashash_last_error", "cashash_plan_schedule", "cashash_last_kernel_ms"]
+            "cashash_last_error", "cashash_plan_schedule", "cashash_last_kernel_ms",
+            "cashash_default_geometric_config", "cashash_subset_size", "cashash_select_top_scale",
+            "cashash_gather_rows", "cashash_estimate_fundamental", "cashash_match_pairs_geometric",
+            "cashash_last_geometric_ms"]
+GEO_ACCEPT, GEO_FEW_MATCHES, GEO_DEGENERATE, GEO_FEW_INLIERS = 0, 1, 2, 3
+GEO_MAX_MATCHES = 8192
 
 
 class Config(C.Structure):
@@ -49,6 +54,12 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class GeoConfig(C.Structure):
+    _fields_ = [("frac_num", C.c_int32), ("frac_den", C.c_int32), ("min_matches", C.c_int32),
+                ("n_hyp", C.c_int32), ("ransac_px", C.c_double), ("band_px", C.c_double),
+                ("rand8", C.c_void_p)]
 
 
 class CashashError(RuntimeError):
@@ -82,8 +93,21 @@ def lib():
         L.cashash_last_error.restype = C.c_char_p
         L.cashash_plan_schedule.argtypes = [I32, P, I64, P, I64, P, P, P, P, P, I64, P]
         L.cashash_last_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.cashash_default_geometric_config.argtypes = [C.POINTER(GeoConfig)]
+        L.cashash_default_geometric_config.restype = None
+        L.cashash_subset_size.argtypes = [I32, I32, I32]
+        L.cashash_subset_size.restype = I64
+        L.cashash_select_top_scale.argtypes = [P, I32, P, P, I32, I32, P]
+        L.cashash_gather_rows.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, P, P]
+        L.cashash_estimate_fundamental.argtypes = [P, I32, P, P, I64, P, P, P, I32, C.c_double, I32,
+                                                   P, P, P, P, P]
+        L.cashash_match_pairs_geometric.argtypes = [P, C.POINTER(Images), P, P, P, P, I64, P, C.POINTER(GeoConfig),
+                                                    P, P, P, P, P, P, P, C.POINTER(Stats)]
+        L.cashash_last_geometric_ms.argtypes = [P, P]
         for f in ("cashash_create", "cashash_set_config", "cashash_build_codes", "cashash_match_pairs",
-                  "cashash_match_pairs_epipolar", "cashash_plan_schedule", "cashash_last_kernel_ms"):
+                  "cashash_match_pairs_epipolar", "cashash_plan_schedule", "cashash_last_kernel_ms",
+                  "cashash_select_top_scale", "cashash_gather_rows", "cashash_estimate_fundamental",
+                  "cashash_match_pairs_geometric", "cashash_last_geometric_ms"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -249,6 +273,99 @@ class Matcher:
             *[(_dptr(a) if self.mem == "device" else (a.ctypes.data if a.size else None)) for a in o],
             C.byref(stats)))
         return o, stats.as_dict()
+
+    # ------------------------------------------------------------ geometry-aware two-stage matching
+    # (device memory only)
+
+    def _need_device(self):
+        if self.mem != "device":
+            raise CashashError(E_INVAL, "geometric calls need mem='device'")
+
+    def select_top_scale(self, scales, frac=(1, 5)):
+        """Rows of the largest-scale features of each image (int32 tensors)."""
+        import torch
+        self._need_device()
+        nf = np.array([int(s.shape[0]) for s in scales], np.int32)
+        rows = [torch.empty(subset_size(n, frac), dtype=torch.int32, device="cuda") for n in nf]
+        check(lib().cashash_select_top_scale(self.h, len(scales), self._arrays(scales), nf.ctypes.data,
+                                             int(frac[0]), int(frac[1]), self._arrays(rows)))
+        return rows
+
+    def gather_rows(self, rows, n_feat, desc=None, codes=None, keys=None, kp=None):
+        """Per-image row gathers of the given fields; returns (desc, codes,
+        keys, kp) lists (None for fields not given)."""
+        import torch
+        self._need_device()
+        nf = np.ascontiguousarray(n_feat, np.int32)
+        nr = np.array([int(r.shape[0]) for r in rows], np.int32)
+        outs, args = [], []
+        for src, tail, dt in ((desc, (128,), torch.uint8), (codes, (2,), torch.int64), (keys, (6,), torch.uint8),
+                              (kp, (2,), torch.float32)):
+            if src is None:
+                outs.append(None)
+                args += [None, None]
+                continue
+            o = [torch.empty((int(n), *tail), dtype=dt, device="cuda") for n in nr]
+            outs.append(o)
+            args += [self._arrays(src), self._arrays(o)]
+        a = args
+        check(lib().cashash_gather_rows(self.h, len(rows), nf.ctypes.data, nr.ctypes.data, self._arrays(rows),
+                                        a[0], a[2], a[4], a[6], a[1], a[3], a[5], a[7]))
+        return tuple(outs)
+
+    def estimate_fundamental(self, n_feat, kp, pairs, match_idx, rand8, thr=2.0, min_matches=16):
+        """Per-pair fundamental matrices from flat stage-1 outputs; returns a
+        dict of numpy arrays (F [P,9], n_matches, n_inliers, best_h, status)."""
+        self._need_device()
+        nf = np.ascontiguousarray(n_feat, np.int32)
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        r = np.ascontiguousarray(rand8, np.uint32).reshape(-1, 8)
+        P = len(pairs)
+        res = dict(F=np.zeros((P, 9)), n_matches=np.zeros(P, np.int32), n_inliers=np.zeros(P, np.int32),
+                   best_h=np.zeros(P, np.int32), status=np.zeros(P, np.int32))
+        check(lib().cashash_estimate_fundamental(
+            self.h, len(nf), nf.ctypes.data, self._arrays(kp), P, pairs.ctypes.data if P else None,
+            _dptr(match_idx), r.ctypes.data, len(r), float(thr), int(min_matches), res["F"].ctypes.data,
+            res["n_matches"].ctypes.data, res["n_inliers"].ctypes.data, res["best_h"].ctypes.data,
+            res["status"].ctypes.data))
+        return res
+
+    def match_pairs_geometric(self, images, codes, keys, kp, scales, pairs, rand8, frac=(1, 5), min_matches=16,
+                              ransac_px=2.0, band_px=4.0, out=None):
+        """Both stages.  Returns ((match_idx, d1sq, d2sq) over all pairs, per-pair
+        dict (F, n_matches, n_inliers, status), stats)."""
+        self._need_device()
+        st, keep = self._images(images)
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        r = np.ascontiguousarray(rand8, np.uint32).reshape(-1, 8)
+        g = GeoConfig()
+        lib().cashash_default_geometric_config(C.byref(g))
+        g.frac_num, g.frac_den, g.min_matches = int(frac[0]), int(frac[1]), int(min_matches)
+        g.n_hyp, g.ransac_px, g.band_px, g.rand8 = len(r), float(ransac_px), float(band_px), r.ctypes.data
+        P = len(pairs)
+        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if P else 0
+        o = self._outputs(n, out)
+        res = dict(F=np.zeros((P, 9)), n_matches=np.zeros(P, np.int32), n_inliers=np.zeros(P, np.int32),
+                   status=np.zeros(P, np.int32))
+        stats = Stats()
+        check(lib().cashash_match_pairs_geometric(
+            self.h, C.byref(st), self._arrays(codes), self._arrays(keys), self._arrays(kp), self._arrays(scales),
+            P, pairs.ctypes.data if P else None, C.byref(g), res["F"].ctypes.data, res["n_matches"].ctypes.data,
+            res["n_inliers"].ctypes.data, res["status"].ctypes.data, *[_dptr(a) for a in o], C.byref(stats)))
+        return o, res, stats.as_dict()
+
+    def last_geometric_ms(self):
+        """Device ms of (subset + gather, stage 1, fundamental, stage 2)."""
+        v = (C.c_double * 4)()
+        check(lib().cashash_last_geometric_ms(self.h, v))
+        return tuple(v)
+
+
+def subset_size(n, frac=(1, 5)) -> int:
+    v = int(lib().cashash_subset_size(int(n), int(frac[0]), int(frac[1])))
+    if v < 0:
+        raise ValueError("need n >= 0 and 0 < frac[0] <= frac[1]")
+    return v
 
 
 def codes_to_numpy(codes):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcashash.so")
-SOURCES = ["cashash_kernels.hip", "cashash_api.hip"]
+SOURCES = ["cashash_kernels.hip", "cashash_match.hip", "cashash_geometry.hip", "cashash_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -135,10 +135,10 @@ struct cashash_ctx {
     // uploaded tables (images, pairs, tiles ...): one double-buffered area for
     // the code builder and one for the matcher, so that the matcher's table
     // addresses (baked into captured launches) do not move between calls
-    DevBuf meta[2][2];
-    HostPinned meta_host[2][2];
-    hipEvent_t meta_ev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    int meta_turn[2] = {0, 0};
+    DevBuf meta[3][2];
+    HostPinned meta_host[3][2];
+    hipEvent_t meta_ev[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    int meta_turn[3] = {0, 0, 0};
     DevBuf near, tables;      // near-margin masks; bucket tables
     DevBuf stage, outbuf;     // host-memory mode: resident image slots; per-step outputs
     HostPinned pin[2];        // host-memory mode upload staging
@@ -166,6 +166,11 @@ struct cashash_ctx {
     std::map<std::string, Shape> tuned;
     bool tune_loaded = false;
     int last_shape_qt = 0, last_shape_bpc = 0;
+    // geometry-aware first stage: subset images, stage-1 outputs, per-pair
+    // results and error flags; stage boundary events of the two-stage call
+    DevBuf geo_sub, geo_m1, geo_pair, geo_err;
+    hipEvent_t geo_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double geo_ms[4] = {0, 0, 0, 0};
 };
 
 static int validate_config(const cashash_config* c) {
@@ -259,14 +264,15 @@ static void destroy_ctx(cashash_ctx* c) {
         hipStreamDestroy(c->copy_stream);
     }
     for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
-                      &c->meta[1][0], &c->meta[1][1], &c->near, &c->tables, &c->stage, &c->outbuf, &c->items,
-                      &c->counters})
+                      &c->meta[1][0], &c->meta[1][1], &c->meta[2][0], &c->meta[2][1], &c->near, &c->tables, &c->stage,
+                      &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err})
         b->release();
     for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
-                          &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
+                          &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
         h->release();
     for (hipEvent_t e : {c->ev0, c->ev1, c->meta_ev[0][0], c->meta_ev[0][1], c->meta_ev[1][0], c->meta_ev[1][1],
-                         c->pin_ev[0], c->pin_ev[1],
+                         c->meta_ev[2][0], c->meta_ev[2][1], c->geo_ev[0], c->geo_ev[1], c->geo_ev[2], c->geo_ev[3],
+                         c->geo_ev[4], c->pin_ev[0], c->pin_ev[1],
                          c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
                          c->slot_free_ev[1], c->slot_free_ev[2]})
         if (e) hipEventDestroy(e);
@@ -338,8 +344,10 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
         return bail(fail(CASHASH_E_DEVICE, "stream/event creation failed"));
-    for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1], &c->pin_ev[0],
-                          &c->pin_ev[1], &c->slot_load_ev[0],
+    for (int i = 0; i < 5; ++i)
+        if (hipEventCreate(&c->geo_ev[i]) != hipSuccess) return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
+    for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1],
+                          &c->meta_ev[2][0], &c->meta_ev[2][1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
                           &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
                           &c->slot_free_ev[2]})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
@@ -375,7 +383,7 @@ static double now_ms() {
 // Uploads small tables on the compute stream (so they follow the kernels that
 // read the previous contents).  Two buffers alternate; a buffer's pinned
 // source is rewritten only after its previous copy has completed.
-enum { kMetaCodes = 0, kMetaMatch = 1 };
+enum { kMetaCodes = 0, kMetaMatch = 1, kMetaGeo = 2 };
 
 static int upload_meta(cashash_ctx* c, Uploader& up, std::vector<const void*>& dptr, int area) {
     const int b = c->meta_turn[area];
@@ -406,6 +414,7 @@ static int check_images(const cashash_images* im) {
 }
 
 static bool misaligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) != 0; }
+static size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // ------------------------------------------------------------------ codes (device-resident core)
 struct CodeJob {
@@ -432,14 +441,20 @@ static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
 // Projection + binary64 fix-up of `imgs` into `outs`, given c->dBias and c->dS.
 static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vector<CodeOut> outs, double n_tot) {
     std::vector<RowChunk> tiles;
-    int64_t flat = 0;
-    for (int m = 0; m < (int)imgs.size(); ++m) {
-        flat += imgs[m].n;
+    for (int m = 0; m < (int)imgs.size(); ++m)
         for (int r0 = 0; r0 < imgs[m].n; r0 += 16) tiles.push_back({m, r0, std::min(16, imgs[m].n - r0), 0});
-    }
     if (tiles.empty()) return CASHASH_OK;
-    // the near list holds at most one entry per descriptor
-    RETCHK(c->near.ensure((size_t)flat * sizeof(NearEntry)));
+    const int nt = (int)tiles.size();
+    const bool mfma = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
+    // near list: one segment per projection wavefront, each large enough for
+    // every descriptor that wavefront handles; per-segment counts in front
+    const int grid = mfma ? std::max(1, std::min((nt + 3) / 4, c->n_cu * 8)) : (int)(((int64_t)nt * 16 + 255) / 256);
+    const uint32_t n_seg = (uint32_t)grid * 4;
+    const uint32_t seg_cap = mfma ? (uint32_t)((nt + n_seg - 1) / n_seg) * 16 : 64;
+    const size_t count_bytes = al256((size_t)n_seg * 4);
+    RETCHK(c->near.ensure(count_bytes + (size_t)n_seg * seg_cap * sizeof(NearEntry)));
+    uint32_t* seg_count = c->near.as<uint32_t>();
+    NearEntry* near = reinterpret_cast<NearEntry*>(c->near.as<uint8_t>() + count_bytes);
     Uploader up;
     up.add(imgs);
     up.add(outs);
@@ -449,20 +464,16 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     const ImgDev* dI = (const ImgDev*)d[0];
     const CodeOut* dO = (const CodeOut*)d[1];
     const RowChunk* dT = (const RowChunk*)d[2];
-    const int nt = (int)tiles.size();
     const float coef = (float)c->cfg.margin_coef;
-    unsigned int* near_count = reinterpret_cast<unsigned int*>(c->dCount.as<unsigned long long>() + 1);
-    HIPCHK(launch_fill_u32(c->stream, near_count, 1, 0u));
-    if (c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2) {
-        const int grid = std::max(1, std::min((nt + 3) / 4, c->n_cu * 8));
+    if (mfma) {
         HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
-                                c->near.as<NearEntry>(), near_count));
+                                near, seg_count, seg_cap));
     } else {
-        HIPCHK(launch_proj_fp32(c->stream, dI, dO, dT, nt, c->dR32.as<float>(), c->dBias.as<float>(), coef,
-                                c->near.as<NearEntry>(), near_count));
+        HIPCHK(launch_proj_fp32(c->stream, dI, dO, dT, nt, c->dR32.as<float>(), c->dBias.as<float>(), coef, near,
+                                seg_count));
     }
-    const int fix_grid = (int)std::max<int64_t>(1, std::min<int64_t>((flat + 255) / 256, (int64_t)c->n_cu * 4));
-    HIPCHK(launch_fixup(c->stream, fix_grid, dI, dO, c->near.as<NearEntry>(), near_count, c->dR64.as<double>(),
+    const int fix_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_seg + 3) / 4, (int64_t)c->n_cu * 4));
+    HIPCHK(launch_fixup(c->stream, fix_grid, dI, dO, near, seg_count, seg_cap, n_seg, c->dR64.as<double>(),
                         c->dS.as<unsigned long long>(), n_tot, c->dCount.as<unsigned long long>()));
     return CASHASH_OK;
 }
@@ -917,7 +928,6 @@ static int finish_match_job(cashash_ctx* c, MatchJob& J) {
 }
 
 // ------------------------------------------------------------------ host-memory mode
-static size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // Chunked upload of caller host memory through two pinned buffers on the copy
 // stream: the CPU fills one buffer while the other is in flight.
@@ -1287,10 +1297,12 @@ extern "C" int cashash_build_codes(cashash_ctx* c, const cashash_images* im, uin
     return CASHASH_OK;
 }
 
+// out_offsets (device mode only): first output slot of each pair; null =
+// pairs packed one after another in list order.
 static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
                         const uint8_t* const* keys, const float* const* kp, int64_t n_pairs, const int32_t* pairs,
                         const double* F, double max_px, bool epi, int32_t* o_idx, int32_t* o_d1, int32_t* o_d2,
-                        cashash_stats* stats) {
+                        cashash_stats* stats, const int64_t* out_offsets = nullptr) {
     if (!c) return fail(CASHASH_E_INVAL, "null context");
     RETCHK(check_images(im));
     if (n_pairs < 0) return fail(CASHASH_E_INVAL, "negative n_pairs");
@@ -1319,7 +1331,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
             return fail(CASHASH_E_INVAL, "pair %lld = (%d, %d) out of range", (long long)p, q, t);
         J.pair_q[p] = q;
         J.pair_t[p] = t;
-        J.pair_out[p] = total_q;
+        J.pair_out[p] = out_offsets ? out_offsets[p] : total_q;
         total_q += im->n_feat[q];
         used[q] = used[t] = 1;
     }
@@ -1334,6 +1346,8 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
     if (total_q > 0 && (!o_idx || !o_d1 || !o_d2)) return fail(CASHASH_E_INVAL, "null output arrays");
     c->last_launches = 0;
     c->last_replayed = false;
+    if (out_offsets && c->cfg.mem != CASHASH_MEM_DEVICE)
+        return fail(CASHASH_E_INVAL, "explicit output offsets need device memory");
     if (c->cfg.mem == CASHASH_MEM_DEVICE) {
         if (misaligned(o_idx, 4) || misaligned(o_d1, 4) || misaligned(o_d2, 4))
             return fail(CASHASH_E_INVAL, "misaligned output arrays");
@@ -1378,3 +1392,382 @@ extern "C" int cashash_match_pairs_epipolar(cashash_ctx* c, const cashash_images
     return match_common(c, im, codes, keys, kp_xy, n_pairs, pairs, F, max_px, true, match_idx, d1sq, d2sq, stats);
 }
 
+// ------------------------------------------------------------------ geometry-aware first stage (Sec. 3.1)
+extern "C" int64_t cashash_subset_size(int32_t n, int32_t frac_num, int32_t frac_den) {
+    if (n < 0 || frac_num <= 0 || frac_den <= 0 || frac_num > frac_den) return -1;
+    return ((int64_t)n * frac_num + frac_den - 1) / frac_den;
+}
+
+extern "C" void cashash_default_geometric_config(cashash_geometric_config* g) {
+    if (!g) return;
+    g->frac_num = 1;
+    g->frac_den = 5;
+    g->min_matches = 16;
+    g->n_hyp = 256;
+    g->ransac_px = 2.0;
+    g->band_px = 4.0;
+    g->rand8 = nullptr;
+}
+
+static int need_device(cashash_ctx* c, const char* what) {
+    if (c->cfg.mem != CASHASH_MEM_DEVICE)
+        return fail(CASHASH_E_INVAL, "%s needs device-resident inputs (cfg.mem = CASHASH_MEM_DEVICE)", what);
+    return CASHASH_OK;
+}
+
+static int check_counts(int32_t n_images, const int32_t* n_feat) {
+    if (n_images < 0 || (n_images > 0 && !n_feat)) return fail(CASHASH_E_INVAL, "invalid image counts");
+    for (int m = 0; m < n_images; ++m) {
+        if (n_feat[m] < 0) return fail(CASHASH_E_INVAL, "image %d: negative n_feat", m);
+        if (n_feat[m] > CASHASH_MAX_FEAT) return fail(CASHASH_E_LIMIT, "image %d: n_feat > %d", m, CASHASH_MAX_FEAT);
+    }
+    return CASHASH_OK;
+}
+
+// Top-scale rows of every image into rows_out[m] (device).
+static int run_select(cashash_ctx* c, int32_t n_images, const float* const* scales, const int32_t* n_feat,
+                      int32_t num, int32_t den, int32_t* const* rows_out) {
+    std::vector<SelectImg> v(n_images);
+    for (int m = 0; m < n_images; ++m) {
+        const int64_t mm = cashash_subset_size(n_feat[m], num, den);
+        if (mm > 0 && (!scales[m] || !rows_out[m]))
+            return fail(CASHASH_E_INVAL, "image %d: null scale or row pointer", m);
+        if (misaligned(scales[m], 4) || misaligned(rows_out[m], 4))
+            return fail(CASHASH_E_INVAL, "image %d: misaligned scale or row buffer", m);
+        v[m] = SelectImg{scales[m], rows_out[m], n_feat[m], (int32_t)mm};
+    }
+    if (n_images == 0) return CASHASH_OK;
+    Uploader up;
+    up.add(v);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d, kMetaGeo));
+    HIPCHK(launch_top_scale(c->stream, (const SelectImg*)d[0], n_images));
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_select_top_scale(cashash_ctx* c, int32_t n_images, const float* const* scales,
+                                        const int32_t* n_feat, int32_t frac_num, int32_t frac_den,
+                                        int32_t* const* rows_out) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(need_device(c, "cashash_select_top_scale"));
+    RETCHK(check_counts(n_images, n_feat));
+    if (cashash_subset_size(0, frac_num, frac_den) < 0) return fail(CASHASH_E_INVAL, "need 0 < frac_num <= frac_den");
+    if (n_images > 0 && (!scales || !rows_out)) return fail(CASHASH_E_INVAL, "null scale or row arrays");
+    RETCHK(run_select(c, n_images, scales, n_feat, frac_num, frac_den, rows_out));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CASHASH_OK;
+}
+
+// Gather of rows; row errors are OR-ed into c->geo_err (not cleared here).
+static int run_gather(cashash_ctx* c, const std::vector<GatherImg>& g) {
+    std::vector<RowChunk> chunks;
+    for (int m = 0; m < (int)g.size(); ++m)
+        for (int r0 = 0; r0 < g[m].m; r0 += 32) chunks.push_back({m, r0, std::min(32, g[m].m - r0), 0});
+    if (chunks.empty()) return CASHASH_OK;
+    Uploader up;
+    up.add(g);
+    up.add(chunks);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d, kMetaGeo));
+    HIPCHK(launch_gather_rows(c->stream, (const GatherImg*)d[0], (const RowChunk*)d[1], (int)chunks.size(),
+                              c->geo_err.as<unsigned>()));
+    return CASHASH_OK;
+}
+
+static int read_geo_err(cashash_ctx* c) {
+    unsigned e = 0;
+    HIPCHK(hipMemcpyAsync(c->pin_small.p, c->geo_err.p, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(&e, c->pin_small.p, 4);
+    if (e & 1u) return fail(CASHASH_E_INVAL, "a row index is outside its image");
+    if (e & 2u) return fail(CASHASH_E_INVAL, "a match index is outside its train image");
+    if (e & 4u) return fail(CASHASH_E_LIMIT, "a pair has more matches than the LDS list holds");
+    return CASHASH_OK;
+}
+
+static int clear_geo_err(cashash_ctx* c) {
+    RETCHK(c->geo_err.ensure(256));
+    HIPCHK(launch_fill_u32(c->stream, c->geo_err.as<uint32_t>(), 1, 0u));
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_gather_rows(cashash_ctx* c, int32_t n_images, const int32_t* n_feat, const int32_t* n_rows,
+                                   const int32_t* const* rows, const uint8_t* const* desc,
+                                   const uint64_t* const* codes, const uint8_t* const* keys, const float* const* kp,
+                                   uint8_t* const* desc_out, uint64_t* const* codes_out, uint8_t* const* keys_out,
+                                   float* const* kp_out) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(need_device(c, "cashash_gather_rows"));
+    RETCHK(check_counts(n_images, n_feat));
+    if (n_images > 0 && (!n_rows || !rows)) return fail(CASHASH_E_INVAL, "null row arrays");
+    if (!desc != !desc_out || !codes != !codes_out || !keys != !keys_out || !kp != !kp_out)
+        return fail(CASHASH_E_INVAL, "each field needs both its input and its output array, or neither");
+    std::vector<GatherImg> g(n_images);
+    for (int m = 0; m < n_images; ++m) {
+        if (n_rows[m] < 0 || n_rows[m] > CASHASH_MAX_FEAT) return fail(CASHASH_E_INVAL, "image %d: bad n_rows", m);
+        GatherImg& x = g[m];
+        x = GatherImg{desc ? desc[m] : nullptr, codes ? codes[m] : nullptr, keys ? keys[m] : nullptr,
+                      kp ? kp[m] : nullptr, rows[m], desc_out ? desc_out[m] : nullptr,
+                      codes_out ? codes_out[m] : nullptr, keys_out ? keys_out[m] : nullptr,
+                      kp_out ? kp_out[m] : nullptr, n_feat[m], n_rows[m]};
+        if (x.m == 0) continue;
+        if (!x.rows || (desc && (!x.desc || !x.o_desc)) || (codes && (!x.codes || !x.o_codes)) ||
+            (keys && (!x.keys || !x.o_keys)) || (kp && (!x.kp || !x.o_kp)))
+            return fail(CASHASH_E_INVAL, "image %d: null buffer", m);
+        if (misaligned(x.rows, 4) || misaligned(x.desc, 16) || misaligned(x.o_desc, 16) || misaligned(x.codes, 8) ||
+            misaligned(x.o_codes, 8) || misaligned(x.keys, 2) || misaligned(x.o_keys, 2) || misaligned(x.kp, 4) ||
+            misaligned(x.o_kp, 4))
+            return fail(CASHASH_E_INVAL, "image %d: misaligned buffer", m);
+    }
+    RETCHK(clear_geo_err(c));
+    RETCHK(run_gather(c, g));
+    return read_geo_err(c);
+}
+
+// Fundamental matrices of `pairs` from the stage-1 outputs `match_idx` (flat,
+// pair p at out[p]) over images of n_feat points with keypoints kp.  Per-pair
+// results go to c->geo_pair: F [P][9] doubles, then n_matches, n_inliers,
+// best_h, status (int32 [P] each).
+static int run_fundamental(cashash_ctx* c, int32_t n_images, const int32_t* n_feat, const float* const* kp,
+                           int64_t n_pairs, const int32_t* pairs, const std::vector<int64_t>& out,
+                           const int32_t* match_idx, const uint32_t* rand8, int32_t n_hyp, double thr,
+                           int32_t min_matches) {
+    std::vector<GeoImg> gi(n_images);
+    for (int m = 0; m < n_images; ++m) gi[m] = GeoImg{kp ? kp[m] : nullptr, n_feat[m], 0};
+    std::vector<GeoPair> gp(n_pairs);
+    int cap = 8;
+    std::vector<char> used(n_images, 0);
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int32_t q = pairs[2 * p], t = pairs[2 * p + 1];
+        gp[p] = GeoPair{q, t, out[p]};
+        cap = std::max(cap, n_feat[q]);
+        used[q] = used[t] = 1;
+    }
+    for (int m = 0; m < n_images; ++m)
+        if (used[m] && n_feat[m] > 0 && (!gi[m].kp || misaligned(gi[m].kp, 4)))
+            return fail(CASHASH_E_INVAL, "image %d: null or misaligned keypoints", m);
+    if (cap > kGeoMaxMatches)
+        return fail(CASHASH_E_LIMIT, "a query image has %d points; at most %d per image here", cap, kGeoMaxMatches);
+    const size_t P = (size_t)n_pairs;
+    RETCHK(c->geo_pair.ensure(P * 9 * 8 + 4 * P * 4 + 256));
+    GeoOut go;
+    go.F = c->geo_pair.as<double>();
+    go.n_matches = reinterpret_cast<int32_t*>(go.F + 9 * P);
+    go.n_inliers = go.n_matches + P;
+    go.best_h = go.n_inliers + P;
+    go.status = go.best_h + P;
+    std::vector<uint32_t> rv(rand8, rand8 + 8 * (size_t)n_hyp);
+    Uploader up;
+    up.add(gi);
+    up.add(gp);
+    up.add(rv);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d, kMetaGeo));
+    GeoParams prm{n_hyp, min_matches, thr, cap, 0};
+    HIPCHK(launch_fundamental(c->stream, (const GeoImg*)d[0], (const GeoPair*)d[1], n_pairs, match_idx,
+                              (const uint32_t*)d[2], prm, go, c->geo_err.as<unsigned>()));
+    return CASHASH_OK;
+}
+
+static int check_geo_args(int32_t n_hyp, const uint32_t* rand8, double thr, int32_t min_matches) {
+    if (n_hyp < 1 || n_hyp > (1 << 20)) return fail(CASHASH_E_INVAL, "n_hyp must be in 1..2^20");
+    if (!rand8) return fail(CASHASH_E_INVAL, "null random draws");
+    if (!(thr >= 0.0) || !std::isfinite(thr)) return fail(CASHASH_E_INVAL, "inlier threshold must be finite and >= 0");
+    if (min_matches < 0) return fail(CASHASH_E_INVAL, "min_matches must be >= 0");
+    return CASHASH_OK;
+}
+
+static int copy_pair_results(cashash_ctx* c, int64_t n_pairs, double* F_out, int32_t* n_matches, int32_t* n_inliers,
+                             int32_t* best_hyp, int32_t* status) {
+    const size_t P = (size_t)n_pairs;
+    const double* F = c->geo_pair.as<double>();
+    const int32_t* nm = reinterpret_cast<const int32_t*>(F + 9 * P);
+    struct Piece {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    for (const Piece& pc : {Piece{F_out, F, P * 72}, Piece{n_matches, nm, P * 4}, Piece{n_inliers, nm + P, P * 4},
+                            Piece{best_hyp, nm + 2 * P, P * 4}, Piece{status, nm + 3 * P, P * 4}})
+        if (pc.dst) HIPCHK(hipMemcpyAsync(pc.dst, pc.src, pc.bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CASHASH_OK;
+}
+
+static int check_pairs(int32_t n_images, int64_t n_pairs, const int32_t* pairs) {
+    if (n_pairs < 0) return fail(CASHASH_E_INVAL, "negative n_pairs");
+    if (n_pairs > 0 && !pairs) return fail(CASHASH_E_INVAL, "null pairs");
+    if (n_pairs > INT32_MAX) return fail(CASHASH_E_LIMIT, "too many pairs");
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int32_t q = pairs[2 * p], t = pairs[2 * p + 1];
+        if (q < 0 || t < 0 || q >= n_images || t >= n_images)
+            return fail(CASHASH_E_INVAL, "pair %lld = (%d, %d) out of range", (long long)p, q, t);
+    }
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_estimate_fundamental(cashash_ctx* c, int32_t n_images, const int32_t* n_feat,
+                                            const float* const* kp_xy, int64_t n_pairs, const int32_t* pairs,
+                                            const int32_t* match_idx, const uint32_t* rand8, int32_t n_hyp,
+                                            double thr_px, int32_t min_matches, double* F_out, int32_t* n_matches,
+                                            int32_t* n_inliers, int32_t* best_hyp, int32_t* status) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(need_device(c, "cashash_estimate_fundamental"));
+    RETCHK(check_counts(n_images, n_feat));
+    RETCHK(check_pairs(n_images, n_pairs, pairs));
+    RETCHK(check_geo_args(n_hyp, rand8, thr_px, min_matches));
+    if (n_pairs == 0) return CASHASH_OK;
+    if (!kp_xy || !F_out || !n_matches || !n_inliers || !status) return fail(CASHASH_E_INVAL, "null argument");
+    std::vector<int64_t> out(n_pairs);
+    int64_t total = 0;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        out[p] = total;
+        total += n_feat[pairs[2 * p]];
+    }
+    if (total > 0 && (!match_idx || misaligned(match_idx, 4)))
+        return fail(CASHASH_E_INVAL, "null or misaligned match_idx");
+    RETCHK(clear_geo_err(c));
+    RETCHK(run_fundamental(c, n_images, n_feat, kp_xy, n_pairs, pairs, out, match_idx, rand8, n_hyp, thr_px,
+                           min_matches));
+    RETCHK(read_geo_err(c));
+    return copy_pair_results(c, n_pairs, F_out, n_matches, n_inliers, best_hyp, status);
+}
+
+extern "C" int cashash_match_pairs_geometric(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                                             const uint8_t* const* keys, const float* const* kp_xy,
+                                             const float* const* scales, int64_t n_pairs, const int32_t* pairs,
+                                             const cashash_geometric_config* g, double* F_out, int32_t* n_matches,
+                                             int32_t* n_inliers, int32_t* status, int32_t* match_idx, int32_t* d1sq,
+                                             int32_t* d2sq, cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    RETCHK(need_device(c, "cashash_match_pairs_geometric"));
+    RETCHK(check_images(im));
+    zero_stats(stats);
+    if (!g) return fail(CASHASH_E_INVAL, "null geometric config");
+    if (cashash_subset_size(0, g->frac_num, g->frac_den) < 0)
+        return fail(CASHASH_E_INVAL, "need 0 < frac_num <= frac_den");
+    RETCHK(check_geo_args(g->n_hyp, g->rand8, g->ransac_px, g->min_matches));
+    if (!(g->band_px >= 0.0) || !std::isfinite(g->band_px)) return fail(CASHASH_E_INVAL, "band_px must be finite and >= 0");
+    RETCHK(check_pairs(im->n_images, n_pairs, pairs));
+    if (n_pairs == 0) return CASHASH_OK;
+    if (!codes || !keys || !kp_xy || !scales || !F_out || !n_matches || !n_inliers || !status)
+        return fail(CASHASH_E_INVAL, "null argument");
+    const double t0 = now_ms();
+    const int n_img = im->n_images;
+    std::vector<char> used(n_img, 0);
+    for (int64_t p = 0; p < n_pairs; ++p) used[pairs[2 * p]] = used[pairs[2 * p + 1]] = 1;
+    // subset sizes and one device block for the subset images
+    std::vector<int32_t> ms(n_img, 0);
+    std::vector<size_t> o_rows(n_img), o_desc(n_img), o_codes(n_img), o_keys(n_img), o_kp(n_img);
+    size_t bytes = 0;
+    auto take = [&](size_t n) {
+        const size_t o = bytes;
+        bytes += al256(n);
+        return o;
+    };
+    for (int m = 0; m < n_img; ++m) {
+        if (!used[m] || im->n_feat[m] == 0) continue;
+        if (!scales[m] || !kp_xy[m] || !codes[m] || !keys[m] || !im->desc[m])
+            return fail(CASHASH_E_INVAL, "image %d: null input buffer", m);
+        ms[m] = (int32_t)cashash_subset_size(im->n_feat[m], g->frac_num, g->frac_den);
+        o_rows[m] = take((size_t)ms[m] * 4);
+        o_desc[m] = take((size_t)ms[m] * kDim);
+        o_codes[m] = take((size_t)ms[m] * 16);
+        o_keys[m] = take((size_t)ms[m] * kTables);
+        o_kp[m] = take((size_t)ms[m] * 8);
+    }
+    RETCHK(c->geo_sub.ensure(bytes));
+    uint8_t* base = c->geo_sub.as<uint8_t>();
+    std::vector<int32_t*> rows(n_img, nullptr);
+    std::vector<uint8_t*> sdesc(n_img, nullptr), skeys(n_img, nullptr);
+    std::vector<uint64_t*> scodes(n_img, nullptr);
+    std::vector<float*> skp(n_img, nullptr);
+    std::vector<GatherImg> gat(n_img);
+    for (int m = 0; m < n_img; ++m) {
+        if (ms[m] > 0) {
+            rows[m] = reinterpret_cast<int32_t*>(base + o_rows[m]);
+            sdesc[m] = base + o_desc[m];
+            scodes[m] = reinterpret_cast<uint64_t*>(base + o_codes[m]);
+            skeys[m] = base + o_keys[m];
+            skp[m] = reinterpret_cast<float*>(base + o_kp[m]);
+        }
+        gat[m] = GatherImg{im->desc[m], codes[m], keys[m], kp_xy[m], rows[m], sdesc[m], scodes[m], skeys[m], skp[m],
+                           im->n_feat[m], ms[m]};
+    }
+    std::vector<int64_t> out1(n_pairs), out2(n_pairs);
+    int64_t total1 = 0, total2 = 0;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        out1[p] = total1;
+        out2[p] = total2;
+        total1 += ms[pairs[2 * p]];
+        total2 += im->n_feat[pairs[2 * p]];
+    }
+    if (total2 > 0 && (!match_idx || !d1sq || !d2sq)) return fail(CASHASH_E_INVAL, "null output arrays");
+    RETCHK(c->geo_m1.ensure((size_t)std::max<int64_t>(total1, 1) * 12));
+    int32_t* m1 = c->geo_m1.as<int32_t>();
+    const size_t T1 = (size_t)std::max<int64_t>(total1, 1);
+
+    // subset selection and gather
+    HIPCHK(hipEventRecord(c->geo_ev[0], c->stream));
+    RETCHK(clear_geo_err(c));
+    std::vector<int32_t> n_sel(n_img);
+    for (int m = 0; m < n_img; ++m) n_sel[m] = ms[m] > 0 ? im->n_feat[m] : 0;
+    RETCHK(run_select(c, n_img, scales, n_sel.data(), g->frac_num, g->frac_den, rows.data()));
+    RETCHK(run_gather(c, gat));
+    HIPCHK(hipEventRecord(c->geo_ev[1], c->stream));
+    // stage 1: CasHash matching of the subsets
+    cashash_images sub{n_img, const_cast<const uint8_t* const*>(sdesc.data()), ms.data()};
+    cashash_stats st1;
+    RETCHK(match_common(c, &sub, const_cast<const uint64_t* const*>(scodes.data()),
+                        const_cast<const uint8_t* const*>(skeys.data()), nullptr, n_pairs, pairs, nullptr, 0.0, false,
+                        m1, m1 + T1, m1 + 2 * T1, &st1));
+    HIPCHK(hipEventRecord(c->geo_ev[2], c->stream));
+    // fundamental matrices from the stage-1 matches
+    RETCHK(run_fundamental(c, n_img, ms.data(), const_cast<const float* const*>(skp.data()), n_pairs, pairs, out1, m1,
+                           g->rand8, g->n_hyp, g->ransac_px, g->min_matches));
+    HIPCHK(hipEventRecord(c->geo_ev[3], c->stream));
+    RETCHK(read_geo_err(c));
+    RETCHK(copy_pair_results(c, n_pairs, F_out, n_matches, n_inliers, nullptr, status));
+    // stage 2: guided matching of the accepted pairs; the others get -1
+    std::vector<int32_t> acc_pairs;
+    std::vector<double> acc_F;
+    std::vector<int64_t> acc_out;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        if (status[p] != 0) continue;
+        acc_pairs.push_back(pairs[2 * p]);
+        acc_pairs.push_back(pairs[2 * p + 1]);
+        acc_F.insert(acc_F.end(), F_out + 9 * p, F_out + 9 * p + 9);
+        acc_out.push_back(out2[p]);
+    }
+    if (total2 > 0) {
+        HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(match_idx), total2, 0xFFFFFFFFu));
+        HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(d1sq), total2, 0xFFFFFFFFu));
+        HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t*>(d2sq), total2, 0xFFFFFFFFu));
+    }
+    cashash_stats st2;
+    zero_stats(&st2);
+    const int64_t n_acc = (int64_t)acc_out.size();
+    if (n_acc > 0)
+        RETCHK(match_common(c, im, codes, keys, kp_xy, n_acc, acc_pairs.data(), acc_F.data(), g->band_px, true,
+                            match_idx, d1sq, d2sq, &st2, acc_out.data()));
+    HIPCHK(hipEventRecord(c->geo_ev[4], c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 4; ++i) {
+        float ms_ = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms_, c->geo_ev[i], c->geo_ev[i + 1]));
+        c->geo_ms[i] = ms_;
+    }
+    if (stats) {
+        *stats = st2;
+        stats->pairs = n_pairs;
+        stats->queries = total2;
+        stats->ms_match = now_ms() - t0;
+    }
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_last_geometric_ms(cashash_ctx* c, double* ms4) {
+    if (!c || !ms4) return fail(CASHASH_E_INVAL, "null argument");
+    for (int i = 0; i < 4; ++i) ms4[i] = c->geo_ms[i];
+    return CASHASH_OK;
+}

@@ -120,4 +120,61 @@ struct ProjParams {
 // vector: frag[part][rt][ks][l][i] = part(R[16 rt + l % 16][32 ks + 8 (l / 16) + i]).
 constexpr int kFragBytes = 2 * kRowTiles * 4 * 64 * 16;
 
+// ---- geometry-aware first stage (Sec. 3.1) ---------------------------------
+
+// Top-scale selection of one image: rows_out[0..m) receives the m largest
+// scales' indices in ascending index order.
+struct SelectImg {
+    const float* scale;  // [n]
+    int32_t* rows_out;   // [m]
+    int32_t n, m;
+};
+
+// Row gather of one image: out row j = in row rows[j]; a null output pointer
+// skips that field.
+struct GatherImg {
+    const uint8_t* desc;    // [n][128]
+    const uint64_t* codes;  // [n][2]
+    const uint8_t* keys;    // [n][6]
+    const float* kp;        // [n][2]
+    const int32_t* rows;    // [m]
+    uint8_t* o_desc;
+    uint64_t* o_codes;
+    uint8_t* o_keys;
+    float* o_kp;
+    int32_t n, m;
+};
+
+// Keypoints of an image the stage-1 matches index.
+struct GeoImg {
+    const float* kp;  // [n][2]
+    int32_t n;
+    int32_t pad;
+};
+
+struct GeoPair {
+    int32_t qi, ti;
+    int64_t out;      // first stage-1 output slot of the pair (n of qi slots)
+};
+
+struct GeoParams {
+    int32_t n_hyp;        // hypotheses (rows of the 8-draw table)
+    int32_t min_matches;  // fewer stage-1 matches: not estimated
+    double thr;           // inlier distance to the epipolar line, px
+    int32_t cap;          // matches held in LDS per pair (>= every pair's query count)
+    int32_t pad;
+};
+
+struct GeoOut {
+    double* F;            // [P][9]
+    int32_t* n_matches;   // [P]
+    int32_t* n_inliers;   // [P]
+    int32_t* best_h;      // [P]
+    int32_t* status;      // [P]
+};
+
+constexpr int kGeoMaxMatches = 8192;  // LDS list of one pair's stage-1 matches (16 B each)
+constexpr int kJacobiSweeps3 = 6;
+constexpr int kJacobiSweeps9 = 10;
+
 }  // namespace cashash

@@ -162,3 +162,68 @@ def test_epipolar_full_size():
     sample = rng.choice(len(w.pairs), size=30, replace=False)
     n = _check_sampled(w, S, N, mats, got, sample, 400, rng, F=True, max_px=w.max_px)
     _say(f"sampled {n} queries equal the oracle")
+
+
+def test_geometric_full_size():
+    """Two-stage matching on 2 scenes x 250 cameras x 12000 features, 15000
+    pairs (a third of them across scenes): per-pair status, match and inlier
+    counts and F for every pair; stage-2 outputs on sampled queries."""
+    from oracle import geometry as G
+    _say("generating geometric set: 2 scenes x 250 cameras x 12000, 15000 pairs")
+    w = synth.geometric_set()
+    mats = synth.projection_matrices()
+    d, kp, sc = _dev_flat(w.images), _dev_flat(w.kp), _dev_flat(w.scales)
+    m = binding.Matcher(*mats, mode="batched", mem="device")
+    codes, keys, _ = m.build_codes(d)
+    rand = np.random.default_rng(7).integers(0, 2**32, (256, 8), dtype=np.uint64).astype(np.uint32)
+    out, res, st = m.match_pairs_geometric(d, codes, keys, kp, sc, w.pairs, rand)
+    got = [o.cpu().numpy() for o in out]
+    ms = m.last_geometric_ms()
+    _say(f"GPU: accepted {int((res['status'] == 0).sum())} of {len(w.pairs)}; ms subset {ms[0]:.2f}, "
+         f"stage 1 {ms[1]:.2f}, F {ms[2]:.2f}, stage 2 {ms[3]:.2f}")
+    # oracle: subsets and their codes, stage 1 over every pair, F for every pair
+    S, N = oracle.column_sums(w.images)
+    rows = [G.top_scale(s) for s in w.scales]
+    sub = [w.images[i][r] for i, r in enumerate(rows)]
+    sc_k = [oracle.project(x, S, N, *mats) for x in sub]
+    m1 = oracle.match_pairs(sub, [c for c, _ in sc_k], [k for _, k in sc_k], w.pairs)
+    nq1 = np.array([len(rows[q]) for q in w.pairs[:, 0]])
+    off1 = np.concatenate([[0], np.cumsum(nq1)])
+    ql, tl = [], []
+    for p, (qi, ti) in enumerate(w.pairs):
+        a, b = G.stage1_points(w.kp[qi][rows[qi]], w.kp[ti][rows[ti]], m1[0][off1[p]:off1[p + 1]])
+        ql.append(a)
+        tl.append(b)
+    est, F, ni, _ = G.fundamental_batch(ql, tl, rand)
+    assert np.array_equal(res["n_matches"], [len(a) for a in ql])
+    assert np.array_equal(res["status"], est)
+    assert np.array_equal(res["n_inliers"], ni)
+    assert np.array_equal(res["F"], F)
+    same = np.array([np.any(f != 0) for f in w.F])
+    _say(f"per-pair results equal the oracle; same-scene accepted {np.mean(est[same] == 0):.3f}, "
+         f"cross-scene accepted {np.mean(est[~same] == 0):.3f}")
+    assert np.mean(est[same] == 0) > 0.95 and np.all(est[~same] != 0)
+    # stage 2 on sampled queries of accepted pairs; rejected pairs are all -1
+    nq = np.array([w.images[q].shape[0] for q in w.pairs[:, 0]])
+    off = np.concatenate([[0], np.cumsum(nq)])
+    rng = np.random.default_rng(3)
+    acc = np.flatnonzero(est == 0)
+    cache = {}
+
+    def full_codes(i):
+        if i not in cache:
+            cache[i] = oracle.project(w.images[i], S, N, *mats)
+        return cache[i]
+
+    for p in rng.choice(acc, size=25, replace=False):
+        qi, ti = (int(x) for x in w.pairs[p])
+        sel = np.sort(rng.choice(nq[p], size=300, replace=False)).astype(np.int32)
+        cq, kq = full_codes(qi)
+        ct, kt = full_codes(ti)
+        exp = oracle.match_pair(w.images[qi], cq, kq, w.images[ti], ct, kt, k=10, q_idx=sel, kp_q=w.kp[qi],
+                                kp_t=w.kp[ti], F=F[p], max_px=w.max_px)
+        for g, e in zip(got, exp):
+            assert np.array_equal(g[off[p] + sel], e), p
+    for p in rng.choice(np.flatnonzero(est != 0), size=20, replace=False):
+        assert all(np.all(g[off[p]:off[p + 1]] == -1) for g in got)
+    _say("sampled stage-2 queries equal the oracle")
