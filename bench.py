@@ -36,9 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": None,
+MEASURED_TRAFFIC = {"sources_sha256": "57cfcc4b7c22891d4e18c2dd240483033cd474d2fd9bd13cc34b1ec94be8a7f3",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": 0, "write_bytes": 0}
+                    "fetch_bytes": int(4673506.8 * 1024 * 2), "write_bytes": int(479179.0 * 1024)}
 
 
 def matcher_sha256():

@@ -110,11 +110,14 @@ __device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t t, u
     const ulonglong2 c = gload(tv.code + pos);
     const uint64_t kid = gload(tv.kid + pos);
     // union: drop the candidate if it shares an earlier table's key with the
-    // query (it was already collected there).  Zero bytes of x = keys ^ qkeys
-    // are found with the carry-free test ((x & 0x7f..) + 0x7f..) | x.
-    const uint64_t x = (kid ^ r.qk) & 0xFFFFFFFFFFFFull;
-    const uint64_t zb = ~(((x & 0x7F7F7F7F7F7Full) + 0x7F7F7F7F7F7Full) | x) & 0x808080808080ull;
-    const bool dup = (zb & ((1ull << (8u * t)) - 1ull)) != 0;
+    // query (it was already collected there): a zero byte among bytes
+    // 0 .. t-1 of keys ^ query keys.  Bytes t.. are forced to 0xFF with
+    // fm = ~0 << 8t, then the exact zero-byte test (v - 0x01..) & ~v & 0x80..
+    // runs on bytes 0-3 and on byte 4 (table 4's key, only below t = 5).
+    const uint64_t fm = ~0ull << (8u * t);
+    const uint32_t y = ((uint32_t)kid ^ (uint32_t)r.qk) | (uint32_t)fm;
+    const uint32_t y4 = ((uint32_t)(kid >> 32) ^ (uint32_t)(r.qk >> 32)) | (uint32_t)(fm >> 32);
+    const bool dup = (((y - 0x01010101u) & ~y) | ((y4 - 0x01010101u) & ~y4 & 0xFFu)) & 0x80808080u;
     bool ok = live && !dup;
     n_union += ok ? 1u : 0u;
     const uint32_t h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
@@ -275,7 +278,9 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             st_bucket += total;
 
             // ---- Steps 1-3, gather: union, Hamming, tau, band; index table
-            clear_hist(hist, lane);
+            // (the histogram over Hamming distance; built during the gather,
+            // except on the band path, where few candidates survive and it is
+            // built only when more than k do)
             uint32_t n_valid = 0;
             constexpr uint32_t kRegCap = 64u * NS;
             uint32_t kr[NS];  // candidate keys held in registers (up to kRegCap)
@@ -283,6 +288,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             for (int u = 0; u < NS; ++u) kr[u] = ~0u;
             bool in_regs = true;
             bool gathered = false;
+            bool hist_built = true;  // false: the index table still has to be built from kr
             if (total == 0) {
                 gathered = true;  // no candidate: nothing to read (the image may have no entries)
             } else if constexpr (EPI) {
@@ -319,16 +325,15 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < NS; ++u) {
-                        const bool keep = kr[u] != ~0u;
-                        if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
-                        n_valid += (uint32_t)__popcll(__ballot(keep));
-                    }
-                    gathered = true;
+                    for (int u = 0; u < NS; ++u) n_valid += (uint32_t)__popcll(__ballot(kr[u] != ~0u));
+                    gathered = true;  // the index table is built only if ranking is needed
                 }
                 wave_sync();
             }
-            if (!gathered) {
+            if (gathered) {
+                hist_built = false;
+            } else {
+                clear_hist(hist, lane);
                 if (total <= kRegCap) {
                     // common case: every bucket entry of the query fits the
                     // register slots; exactly ceil(total / 64) chunks are read
@@ -415,58 +420,69 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
         }                                                                                             \
     } while (0)
 
-            // ---- Step 3: Hamming distance H* of the kk-th candidate from the index table
-            uint32_t below;
-            const uint32_t hs = hist_select(hist, kk, lane, &below);
-            const uint32_t need = kk - below;
-            const uint32_t ties = readlane(hist[hs], 0);
             uint32_t tkey;  // kept candidates: key <= tkey
-            if (ties == need) {
-                tkey = ((hs + 1u) << 16) - 1u;
-            } else if (ties <= 64) {
-                // few ties: gather their indices (the index table is no longer
-                // needed) and rank each one against the others
-                const uint32_t lo = hs << 16, hi = lo + 0x10000u;
-                uint32_t nt = 0;
-                if (in_regs) {
-#pragma unroll
-                    for (int u = 0; u < NS; ++u) {
-                        const bool tie = kr[u] >= lo && kr[u] < hi;
-                        const uint64_t mk = __ballot(tie);
-                        const uint32_t slot = nt + mbcnt64(mk);
-                        if (tie && slot < 256u) hist[slot] = kr[u] & 0xFFFFu;
-                        nt += (uint32_t)__popcll(mk);
-                    }
-                } else {
-                    for (uint32_t base = 0; base < span; base += 64) {
-                        const uint32_t e = base + lane;
-                        const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                     : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
-                        const bool tie = key >= lo && key < hi;
-                        const uint64_t mk = __ballot(tie);
-                        const uint32_t slot = nt + mbcnt64(mk);
-                        if (tie && slot < 256u) hist[slot] = key & 0xFFFFu;
-                        nt += (uint32_t)__popcll(mk);
-                    }
-                }
-                wave_sync();
-                const uint32_t jl = (uint32_t)lane < ties ? hist[lane] : ~0u;
-                uint32_t rank = 0;
-                for (uint32_t m = 0; m < ties; ++m) rank += hist[m] < jl ? 1u : 0u;
-                const uint64_t pick = __ballot((uint32_t)lane < ties && rank == need - 1u);
-                tkey = lo | readlane(jl, __ffsll((unsigned long long)pick) - 1);
+            if (n_valid <= (uint32_t)prm.k) {
+                tkey = 0xFFFFFFFEu;  // every valid candidate is kept; no ranking needed
             } else {
-                // many ties: the need-th smallest index among them, by counting
-                // with ballots over a binary search of the index bits
-                const uint32_t lo = hs << 16;
-                uint32_t J = 0;
-                for (int b = (int)jbits - 1; b >= 0; --b) {
-                    const uint32_t J2 = J | (1u << b);
-                    uint32_t cnt;
-                    COUNT_RANGE(lo, lo | J2, cnt);
-                    if (cnt < need) J = J2;
+                if (!hist_built) {
+                    clear_hist(hist, lane);
+#pragma unroll
+                    for (int u = 0; u < NS; ++u)
+                        if (kr[u] != ~0u) atomicAdd(&hist[kr[u] >> 16], 1u);
+                    wave_sync();
                 }
-                tkey = lo | J;
+                // ---- Step 3: Hamming distance H* of the kk-th candidate from the index table
+                uint32_t below;
+                const uint32_t hs = hist_select(hist, kk, lane, &below);
+                const uint32_t need = kk - below;
+                const uint32_t ties = readlane(hist[hs], 0);
+                if (ties == need) {
+                    tkey = ((hs + 1u) << 16) - 1u;
+                } else if (ties <= 64) {
+                    // few ties: gather their indices (the index table is no longer
+                    // needed) and rank each one against the others
+                    const uint32_t lo = hs << 16, hi = lo + 0x10000u;
+                    uint32_t nt = 0;
+                    if (in_regs) {
+#pragma unroll
+                        for (int u = 0; u < NS; ++u) {
+                            const bool tie = kr[u] >= lo && kr[u] < hi;
+                            const uint64_t mk = __ballot(tie);
+                            const uint32_t slot = nt + mbcnt64(mk);
+                            if (tie && slot < 256u) hist[slot] = kr[u] & 0xFFFFu;
+                            nt += (uint32_t)__popcll(mk);
+                        }
+                    } else {
+                        for (uint32_t base = 0; base < span; base += 64) {
+                            const uint32_t e = base + lane;
+                            const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
+                                                         : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
+                            const bool tie = key >= lo && key < hi;
+                            const uint64_t mk = __ballot(tie);
+                            const uint32_t slot = nt + mbcnt64(mk);
+                            if (tie && slot < 256u) hist[slot] = key & 0xFFFFu;
+                            nt += (uint32_t)__popcll(mk);
+                        }
+                    }
+                    wave_sync();
+                    const uint32_t jl = (uint32_t)lane < ties ? hist[lane] : ~0u;
+                    uint32_t rank = 0;
+                    for (uint32_t m = 0; m < ties; ++m) rank += hist[m] < jl ? 1u : 0u;
+                    const uint64_t pick = __ballot((uint32_t)lane < ties && rank == need - 1u);
+                    tkey = lo | readlane(jl, __ffsll((unsigned long long)pick) - 1);
+                } else {
+                    // many ties: the need-th smallest index among them, by counting
+                    // with ballots over a binary search of the index bits
+                    const uint32_t lo = hs << 16;
+                    uint32_t J = 0;
+                    for (int b = (int)jbits - 1; b >= 0; --b) {
+                        const uint32_t J2 = J | (1u << b);
+                        uint32_t cnt;
+                        COUNT_RANGE(lo, lo | J2, cnt);
+                        if (cnt < need) J = J2;
+                    }
+                    tkey = lo | J;
+                }
             }
             // compaction of the kept candidates into the tile list
             if (in_regs) {
