@@ -191,6 +191,35 @@ def geometric_leg(binding, synth, torch, steps, cpu_seconds, no_cpu):
     return out
 
 
+def disk_leg(binding, w, mats, budget_bytes):
+    """The three-level path on the bench set: set file on local disk, codes
+    and matches streamed through host groups of budget_bytes / 3."""
+    import tempfile
+    d = tempfile.mkdtemp(prefix="cashash_disk_")
+    set_path, codes_path, out_path = (os.path.join(d, f) for f in ("set.chs", "codes.chc", "out.cho"))
+    try:
+        binding.set_write(set_path, w.images)
+        m = binding.Matcher(*mats, mem="host")
+        t0 = time.perf_counter()
+        stc = m.build_codes_disk(set_path, codes_path, budget_bytes)
+        t1 = time.perf_counter()
+        left, stm = m.match_pairs_disk(set_path, codes_path, w.pairs, out_path, budget_bytes)
+        t2 = time.perf_counter()
+        m.close()
+        P = len(w.pairs)
+        return {"host_budget_bytes": budget_bytes, "pairs_per_s": round(P / (t2 - t0), 1),
+                "match_pairs_per_s": round(P / (t2 - t1), 1), "s_codes": round(t1 - t0, 3),
+                "s_match": round(t2 - t1, 3), "group_loads": stc["group_loads"] + stm["group_loads"],
+                "disk_bytes": stc["disk_bytes"] + stm["disk_bytes"], "h2d_bytes": stc["h2d_bytes"] + stm["h2d_bytes"],
+                "steps_left": left, "note": "files in the system temp directory; includes disk reads, uploads, "
+                                            "downloads and output writes"}
+    finally:
+        for f in (set_path, codes_path, out_path):
+            if os.path.exists(f):
+                os.remove(f)
+        os.rmdir(d)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +234,8 @@ def main():
                     help="also match with Hamming thresholds tau in 128..32 (ranking section) and report matches/time")
     ap.add_argument("--geometric", action="store_true",
                     help="also run the two-stage geometry-aware form on 2 scenes x 250 cameras x 12000 features")
+    ap.add_argument("--disk", type=int, default=0, metavar="MB",
+                    help="also run the disk level (set file, host groups within MB megabytes) on the bench set")
     ap.add_argument("--geometric-only", action="store_true",
                     help="run only the two-stage form (for profiling) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -328,6 +359,10 @@ def main():
             mt.close()
         result["tau_sweep"] = sweep
     m.close()
+    if args.disk:
+        log(f"disk level, host budget {args.disk} MB")
+        result["disk"] = disk_leg(binding, w, mats, args.disk << 20)
+        log(f"disk: {result['disk']}")
     if args.geometric:
         result["geometric"] = geometric_leg(binding, synth, torch, args.steps, args.cpu_seconds, args.no_cpu)
     if not args.no_cpu:

@@ -47,6 +47,7 @@ extern "C" {
 #define CASHASH_E_DEVICE (-3)         /* a HIP call failed */
 #define CASHASH_E_UNSAFE_MATRIX (-4)  /* a projection row is too long for the fast-path margin proof */
 #define CASHASH_E_LIMIT (-5)          /* n_feat > 65535, k outside 1..64, or another hard limit */
+#define CASHASH_E_IO (-6)             /* a file could not be opened, read or written, or has a bad header */
 
 #define CASHASH_MODE_BATCHED_BF16X2 0      /* BF16 hi+lo MFMA projection; all pairs in one persistent launch */
 #define CASHASH_MODE_PLAIN_FP32_PER_PAIR 1 /* FP32 VALU projection; one launch set per image pair */
@@ -89,6 +90,8 @@ typedef struct {
     int64_t blocks_per_cu;          /*   persistent blocks per compute unit (0 in the plain form) */
     int64_t graph_replayed;         /* 1 if the batched matcher ran as a replay of a captured HIP graph */
     double ms_codes, ms_match;      /* wall time of the call */
+    int64_t disk_bytes;             /* disk level: bytes read from the set and codes files */
+    int64_t group_loads;            /* disk level: groups read into host memory */
 } cashash_stats;
 
 /* Fill cfg with the defaults above. */
@@ -286,6 +289,56 @@ int cashash_match_pairs_geometric(cashash_ctx* ctx, const cashash_images* images
                                   int64_t n_pairs, const int32_t* pairs, const cashash_geometric_config* g,
                                   double* F_out, int32_t* n_matches, int32_t* n_inliers, int32_t* status,
                                   int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats);
+
+/* ---- Disk level of the data scheduling ("Three-Level Data Scheduling
+ * Strategy": disk -> host memory -> GPU) ------------------------------------
+ *
+ * The image set lives in a file; groups of images are read into host memory
+ * under host_budget_bytes while a second thread reads the next group ahead,
+ * and each group (pair of groups) goes through the host-memory path, which
+ * streams blocks to the device under cfg.device_budget_bytes.  These calls
+ * need cfg.mem == CASHASH_MEM_HOST (else E_INVAL).  Files, little-endian,
+ * headers padded to 64 bytes:
+ *   set file    "CASHSET1", int64 n_images, int64 flags (bit 0: keypoints),
+ *               int64 prefix sums of the feature counts [n_images + 1], then
+ *               at the next multiple of 64 bytes uint8 descriptors [N][128]
+ *               (N = total features) and, if flagged, float32 keypoints [N][2]
+ *   codes file  "CASHCOD1", int64 n_images, int64 N; at byte 64 uint64 codes
+ *               [N][2], then uint8 keys [N][6]
+ *   output file "CASHOUT1", int64 n_pairs, int64 T (total queries); at byte 64
+ *               int32 match_idx [T], d1sq [T], d2sq [T] in the flat layout of
+ *               cashash_match_pairs
+ *   progress    "CASHPRG1", uint64 plan hash, int64 n_steps; at byte 64 one
+ *               byte per group pair, 1 once its outputs are written and synced
+ * File errors return CASHASH_E_IO. */
+
+/* Write the set file of host images (kp_xy may be NULL). */
+int cashash_set_write(const char* path, const cashash_images* images, const float* const* kp_xy);
+
+/* Codes and keys of every descriptor of the set file (as cashash_build_codes
+ * over the whole set: centred on the mean of all N descriptors) into
+ * codes_path.  Two passes over groups of consecutive images, each group at
+ * most host_budget_bytes / 2 of descriptors: column sums, then codes.
+ * stats: disk_bytes, group_loads, near_margin_recomputes, h2d/d2h bytes. */
+int cashash_build_codes_disk(cashash_ctx* ctx, const char* set_path, const char* codes_path,
+                             int64_t host_budget_bytes, cashash_stats* stats);
+
+/* Match the pairs of a set file against its codes file, writing out_path.
+ * Groups hold at most host_budget_bytes / 3 (descriptors, codes and keys);
+ * group pairs are visited in the scheduler's order ((i, i+1) .. (i, last),
+ * then (i, i)) with two groups in progress and one read ahead.  After each
+ * group pair its outputs are written and synced, then its byte in the
+ * progress file (progress_path may be NULL: no resume and no syncing).
+ * Outputs are written by a second thread while the next group pair runs.  A call with the same
+ * set, pairs and budget skips the group pairs already marked, so an
+ * interrupted run resumes where it stopped; any other progress file is reset.
+ * max_steps > 0 stops after that many group pairs (0 = run to the end);
+ * *steps_left (may be NULL) receives the number still to do.  The outputs
+ * equal cashash_match_pairs over the same images and pairs. */
+int cashash_match_pairs_disk(cashash_ctx* ctx, const char* set_path, const char* codes_path, int64_t n_pairs,
+                             const int32_t* pairs, const char* out_path, const char* progress_path,
+                             int64_t host_budget_bytes, int64_t max_steps, int64_t* steps_left,
+                             cashash_stats* stats);
 
 /* Device time of the last cashash_match_pairs_geometric call's four parts,
  * in milliseconds (HIP events on its stream): subset selection and gather,

@@ -20,7 +20,7 @@ from . import synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcashash.so")
 
-OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSAFE_MATRIX, E_LIMIT = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSAFE_MATRIX, E_LIMIT, E_IO = 0, -1, -2, -3, -4, -5, -6
 MODE_BATCHED_BF16X2, MODE_PLAIN_FP32_PER_PAIR = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 MODES = {"batched": MODE_BATCHED_BF16X2, "plain": MODE_PLAIN_FP32_PER_PAIR}
@@ -30,7 +30,8 @@ EXPORTED = ["cashash_default_config", "cashash_create", "cashash_set_config", "c
             "cashash_last_error", "cashash_plan_schedule", "cashash_last_kernel_ms",
             "cashash_default_geometric_config", "cashash_subset_size", "cashash_select_top_scale",
             "cashash_gather_rows", "cashash_estimate_fundamental", "cashash_match_pairs_geometric",
-            "cashash_last_geometric_ms"]
+            "cashash_last_geometric_ms", "cashash_set_write", "cashash_build_codes_disk",
+            "cashash_match_pairs_disk"]
 GEO_ACCEPT, GEO_FEW_MATCHES, GEO_DEGENERATE, GEO_FEW_INLIERS = 0, 1, 2, 3
 GEO_MAX_MATCHES = 8192
 
@@ -50,7 +51,8 @@ class Stats(C.Structure):
                 ("union_size", C.c_int64), ("ranked", C.c_int64), ("near_margin_recomputes", C.c_int64),
                 ("h2d_bytes", C.c_int64), ("d2h_bytes", C.c_int64), ("image_loads", C.c_int64),
                 ("tile_queries", C.c_int64), ("blocks_per_cu", C.c_int64), ("graph_replayed", C.c_int64),
-                ("ms_codes", C.c_double), ("ms_match", C.c_double)]
+                ("ms_codes", C.c_double), ("ms_match", C.c_double), ("disk_bytes", C.c_int64),
+                ("group_loads", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,10 +106,15 @@ def lib():
         L.cashash_match_pairs_geometric.argtypes = [P, C.POINTER(Images), P, P, P, P, I64, P, C.POINTER(GeoConfig),
                                                     P, P, P, P, P, P, P, C.POINTER(Stats)]
         L.cashash_last_geometric_ms.argtypes = [P, P]
+        L.cashash_set_write.argtypes = [C.c_char_p, C.POINTER(Images), P]
+        L.cashash_build_codes_disk.argtypes = [P, C.c_char_p, C.c_char_p, I64, C.POINTER(Stats)]
+        L.cashash_match_pairs_disk.argtypes = [P, C.c_char_p, C.c_char_p, I64, P, C.c_char_p, C.c_char_p, I64, I64,
+                                               C.POINTER(C.c_int64), C.POINTER(Stats)]
         for f in ("cashash_create", "cashash_set_config", "cashash_build_codes", "cashash_match_pairs",
                   "cashash_match_pairs_epipolar", "cashash_plan_schedule", "cashash_last_kernel_ms",
                   "cashash_select_top_scale", "cashash_gather_rows", "cashash_estimate_fundamental",
-                  "cashash_match_pairs_geometric", "cashash_last_geometric_ms"):
+                  "cashash_match_pairs_geometric", "cashash_last_geometric_ms", "cashash_set_write",
+                  "cashash_build_codes_disk", "cashash_match_pairs_disk"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -274,6 +281,26 @@ class Matcher:
             C.byref(stats)))
         return o, stats.as_dict()
 
+    # ------------------------------------------------------------ disk level (mem="host" only)
+    def build_codes_disk(self, set_path, codes_path, host_budget_bytes):
+        stats = Stats()
+        check(lib().cashash_build_codes_disk(self.h, os.fsencode(set_path), os.fsencode(codes_path),
+                                             int(host_budget_bytes), C.byref(stats)))
+        return stats.as_dict()
+
+    def match_pairs_disk(self, set_path, codes_path, pairs, out_path, host_budget_bytes, progress_path=None,
+                         max_steps=0):
+        """Returns (steps_left, stats)."""
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        left = C.c_int64(0)
+        stats = Stats()
+        check(lib().cashash_match_pairs_disk(
+            self.h, os.fsencode(set_path), os.fsencode(codes_path), len(pairs),
+            pairs.ctypes.data if len(pairs) else None, os.fsencode(out_path),
+            os.fsencode(progress_path) if progress_path else None, int(host_budget_bytes), int(max_steps),
+            C.byref(left), C.byref(stats)))
+        return left.value, stats.as_dict()
+
     # ------------------------------------------------------------ geometry-aware two-stage matching
     # (device memory only)
 
@@ -359,6 +386,36 @@ class Matcher:
         v = (C.c_double * 4)()
         check(lib().cashash_last_geometric_ms(self.h, v))
         return tuple(v)
+
+
+def set_write(path, images, kp=None):
+    """Write the set file of host (numpy) images, with optional keypoints."""
+    images = [np.ascontiguousarray(im, np.uint8).reshape(-1, 128) for im in images]
+    nf = np.array([im.shape[0] for im in images], np.int32)
+    ptrs = _ptrs([im.ctypes.data if im.size else None for im in images])
+    st = Images(len(images), C.cast(ptrs, C.POINTER(C.c_void_p)), nf.ctypes.data_as(C.POINTER(C.c_int32)))
+    kpp = None
+    if kp is not None:
+        kp = [np.ascontiguousarray(a, np.float32).reshape(-1, 2) for a in kp]
+        kpp = _ptrs([a.ctypes.data if a.size else None for a in kp])
+    check(lib().cashash_set_write(os.fsencode(path), C.byref(st), kpp))
+
+
+def read_codes_file(path):
+    """(codes uint64 [N, 2], keys uint8 [N, 6]) of a codes file."""
+    hdr = np.fromfile(path, np.int64, count=3, offset=0)
+    n = int(hdr[2])
+    codes = np.fromfile(path, np.uint64, count=2 * n, offset=64).reshape(n, 2)
+    keys = np.fromfile(path, np.uint8, count=6 * n, offset=64 + 16 * n).reshape(n, 6)
+    return codes, keys
+
+
+def read_output_file(path):
+    """(match_idx, d1sq, d2sq) int32 arrays of an output file."""
+    hdr = np.fromfile(path, np.int64, count=3, offset=0)
+    t = int(hdr[2])
+    a = np.fromfile(path, np.int32, count=3 * t, offset=64)
+    return a[:t], a[t:2 * t], a[2 * t:]
 
 
 def subset_size(n, frac=(1, 5)) -> int:

@@ -17,6 +17,13 @@
 #include <string>
 #include <vector>
 
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <future>
+#include <thread>
+
 #include "cashash.h"
 #include "cashash_internal.h"
 #include "cashash_launch.h"
@@ -973,14 +980,23 @@ static SlotImage slot_layout(int n, bool with_codes, bool with_kp) {
 // Codes: pass 1 streams every block for the column sums, pass 2 streams the
 // blocks again (last block first, so the one still resident is reused) to
 // project them.  Two slots: one in use, one being filled.
+// Passes of the host-mode code builder.  Both (the default) clears the sums,
+// sums every block, sets the bias and projects.  kPassSums alone adds these
+// images' column sums to c->dS; kPassCodes alone projects them with the bias
+// already set for a whole set of n_tot_set descriptors (the disk level runs
+// the two over groups of a larger set).
+enum { kPassSums = 1, kPassCodes = 2 };
+
 static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* const* codes_out,
-                            uint8_t* const* keys_out, int64_t* near_count, cashash_stats* stats) {
+                            uint8_t* const* keys_out, int64_t* near_count, cashash_stats* stats,
+                            int passes = kPassSums | kPassCodes, double n_tot_set = 0.0) {
+    const bool both = passes == (kPassSums | kPassCodes);
     const int M = im->n_images;
     double n_tot = 0;
     std::vector<int64_t> bytes(M);
     for (int m = 0; m < M; ++m) {
         const int n = im->n_feat[m];
-        if (n > 0 && (!im->desc[m] || !codes_out[m] || !keys_out[m]))
+        if (n > 0 && (!im->desc[m] || ((passes & kPassCodes) && (!codes_out[m] || !keys_out[m]))))
             return fail(CASHASH_E_INVAL, "image %d: null descriptor or output pointer", m);
         bytes[m] = (int64_t)slot_layout(n, true, false).end;
         n_tot += n;
@@ -1034,26 +1050,32 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
             ov.push_back(CodeOut{reinterpret_cast<uint64_t*>(base + L.codes), base + L.keys, 0});
         }
     };
-    HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
-    HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
     std::vector<ImgDev> iv;
     std::vector<CodeOut> ov;
-    for (int b = 0; b < nb; ++b) {
-        const int s = b & 1;
-        RETCHK(load(b, s));
-        HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
-        views(b, iv, ov);
-        RETCHK(run_colsum(c, iv));
-        HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
-        if (b + 1 < nb) RETCHK(load(b + 1, (b + 1) & 1));  // prefetch while the sums run
+    if (both) {
+        HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
+        HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
     }
-    HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot, c->dBias.as<float>()));
-    for (int b = nb - 1; b >= 0; --b) {
+    if (passes & kPassSums) {
+        for (int b = 0; b < nb; ++b) {
+            const int s = b & 1;
+            RETCHK(load(b, s));
+            HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
+            views(b, iv, ov);
+            RETCHK(run_colsum(c, iv));
+            HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
+            if (b + 1 < nb) RETCHK(load(b + 1, (b + 1) & 1));  // prefetch while the sums run
+        }
+    }
+    if (both)
+        HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot,
+                           c->dBias.as<float>()));
+    for (int b = nb - 1; (passes & kPassCodes) && b >= 0; --b) {
         int s = resident[0] == b ? 0 : resident[1] == b ? 1 : (b & 1);
         RETCHK(load(b, s));
         HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
         views(b, iv, ov);
-        RETCHK(run_project(c, iv, ov, n_tot));
+        RETCHK(run_project(c, iv, ov, both ? n_tot : n_tot_set));
         size_t out_bytes = 0;
         for (int m = first[b]; m < first[b + 1]; ++m) out_bytes += (size_t)im->n_feat[m] * 22;
         RETCHK(c->pin_out.ensure(out_bytes));
@@ -1082,12 +1104,13 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
         }
     }
     unsigned long long cnt = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(&cnt, c->dCount.p, 8, hipMemcpyDeviceToHost));
     *near_count = (int64_t)cnt;
     if (stats) {
-        stats->h2d_bytes = h2d;
-        stats->d2h_bytes = d2h;
-        stats->image_loads = loads;
+        stats->h2d_bytes += h2d;
+        stats->d2h_bytes += d2h;
+        stats->image_loads += loads;
     }
     return CASHASH_OK;
 }
@@ -1769,5 +1792,517 @@ extern "C" int cashash_match_pairs_geometric(cashash_ctx* c, const cashash_image
 extern "C" int cashash_last_geometric_ms(cashash_ctx* c, double* ms4) {
     if (!c || !ms4) return fail(CASHASH_E_INVAL, "null argument");
     for (int i = 0; i < 4; ++i) ms4[i] = c->geo_ms[i];
+    return CASHASH_OK;
+}
+
+// ------------------------------------------------------------------ disk level ("Three-Level Data Scheduling Strategy")
+// The whole set lives on disk; groups of images are read into host memory by
+// a second thread while the current group (pair) is processed, and each
+// group (pair) is handed to the host-memory path, which streams blocks to
+// the device.  File layouts (little-endian, headers padded to 64 bytes):
+//   set    "CASHSET1", n_images, flags (bit 0: keypoints), feature prefix
+//          sums [n_images + 1], then at a 64-byte boundary the descriptors
+//          uint8 [N][128] and, if flagged, keypoints float32 [N][2]
+//   codes  "CASHCOD1", n_images, N; at 64: codes uint64 [N][2], keys uint8 [N][6]
+//   output "CASHOUT1", n_pairs, total queries T; at 64: match_idx, d1sq, d2sq int32 [T] each
+//   progress "CASHPRG1", plan hash, n_steps; at 64: one byte per group pair (1 = written)
+namespace {
+
+const char kSetMagic[8] = {'C', 'A', 'S', 'H', 'S', 'E', 'T', '1'};
+const char kCodMagic[8] = {'C', 'A', 'S', 'H', 'C', 'O', 'D', '1'};
+const char kOutMagic[8] = {'C', 'A', 'S', 'H', 'O', 'U', 'T', '1'};
+const char kPrgMagic[8] = {'C', 'A', 'S', 'H', 'P', 'R', 'G', '1'};
+constexpr int64_t kFileHeader = 64;
+
+struct Fd {
+    int fd = -1;
+    Fd() = default;
+    Fd(const Fd&) = delete;
+    Fd& operator=(const Fd&) = delete;
+    ~Fd() {
+        if (fd >= 0) ::close(fd);
+    }
+};
+
+bool read_at(int fd, void* buf, size_t n, int64_t off) {
+    uint8_t* p = static_cast<uint8_t*>(buf);
+    while (n > 0) {
+        const ssize_t r = ::pread(fd, p, n, (off_t)off);
+        if (r <= 0) return false;
+        p += r;
+        n -= (size_t)r;
+        off += r;
+    }
+    return true;
+}
+
+bool write_at(int fd, const void* buf, size_t n, int64_t off) {
+    const uint8_t* p = static_cast<const uint8_t*>(buf);
+    while (n > 0) {
+        const ssize_t r = ::pwrite(fd, p, n, (off_t)off);
+        if (r <= 0) return false;
+        p += r;
+        n -= (size_t)r;
+        off += r;
+    }
+    return true;
+}
+
+int64_t al64(int64_t n) { return (n + 63) & ~int64_t(63); }
+
+struct SetFile {
+    Fd f;
+    int32_t n_images = 0;
+    int64_t flags = 0;
+    std::vector<int64_t> offs;  // feature prefix sums
+    int64_t desc_off = 0;
+    std::vector<int32_t> n_feat;
+};
+
+int open_set(const char* path, SetFile& s) {
+    if (!path) return fail(CASHASH_E_INVAL, "null set path");
+    s.f.fd = ::open(path, O_RDONLY);
+    if (s.f.fd < 0) return fail(CASHASH_E_IO, "cannot open set file %s", path);
+    char magic[8];
+    int64_t hdr[2];
+    if (!read_at(s.f.fd, magic, 8, 0) || std::memcmp(magic, kSetMagic, 8) != 0 || !read_at(s.f.fd, hdr, 16, 8))
+        return fail(CASHASH_E_IO, "%s is not a set file", path);
+    if (hdr[0] < 0 || hdr[0] > INT32_MAX) return fail(CASHASH_E_IO, "%s: bad image count", path);
+    s.n_images = (int32_t)hdr[0];
+    s.flags = hdr[1];
+    s.offs.resize((size_t)s.n_images + 1);
+    if (!read_at(s.f.fd, s.offs.data(), s.offs.size() * 8, 24)) return fail(CASHASH_E_IO, "%s: short header", path);
+    s.n_feat.resize(s.n_images);
+    if (s.offs[0] != 0) return fail(CASHASH_E_IO, "%s: bad offsets", path);
+    for (int m = 0; m < s.n_images; ++m) {
+        const int64_t n = s.offs[m + 1] - s.offs[m];
+        if (n < 0 || n > CASHASH_MAX_FEAT) return fail(CASHASH_E_IO, "%s: image %d has a bad feature count", path, m);
+        s.n_feat[m] = (int32_t)n;
+    }
+    s.desc_off = al64(24 + 8 * ((int64_t)s.n_images + 1));
+    struct stat st;
+    if (::fstat(s.f.fd, &st) != 0 || st.st_size < s.desc_off + s.offs.back() * kDim)
+        return fail(CASHASH_E_IO, "%s is shorter than its header says", path);
+    return CASHASH_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" int cashash_set_write(const char* path, const cashash_images* im, const float* const* kp_xy) {
+    RETCHK(check_images(im));
+    if (!path) return fail(CASHASH_E_INVAL, "null path");
+    const int M = im->n_images;
+    std::vector<int64_t> offs((size_t)M + 1, 0);
+    for (int m = 0; m < M; ++m) {
+        if (im->n_feat[m] > 0 && (!im->desc[m] || (kp_xy && !kp_xy[m])))
+            return fail(CASHASH_E_INVAL, "image %d: null buffer", m);
+        offs[m + 1] = offs[m] + im->n_feat[m];
+    }
+    Fd f;
+    f.fd = ::open(path, O_WRONLY | O_CREAT | O_TRUNC, 0644);
+    if (f.fd < 0) return fail(CASHASH_E_IO, "cannot create %s", path);
+    const int64_t hdr[2] = {(int64_t)M, kp_xy ? 1 : 0};
+    const int64_t desc_off = al64(24 + 8 * ((int64_t)M + 1));
+    bool ok = write_at(f.fd, kSetMagic, 8, 0) && write_at(f.fd, hdr, 16, 8) &&
+              write_at(f.fd, offs.data(), offs.size() * 8, 24);
+    const int64_t N = offs.back();
+    for (int m = 0; ok && m < M; ++m)
+        if (im->n_feat[m] > 0)
+            ok = write_at(f.fd, im->desc[m], (size_t)im->n_feat[m] * kDim, desc_off + offs[m] * kDim);
+    for (int m = 0; ok && kp_xy && m < M; ++m)
+        if (im->n_feat[m] > 0)
+            ok = write_at(f.fd, kp_xy[m], (size_t)im->n_feat[m] * 8, desc_off + N * kDim + offs[m] * 8);
+    if (ok && N == 0) ok = ::ftruncate(f.fd, (off_t)desc_off) == 0;
+    if (!ok) return fail(CASHASH_E_IO, "write to %s failed", path);
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_build_codes_disk(cashash_ctx* c, const char* set_path, const char* codes_path,
+                                        int64_t host_budget_bytes, cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    if (c->cfg.mem != CASHASH_MEM_HOST) return fail(CASHASH_E_INVAL, "the disk level needs cfg.mem = CASHASH_MEM_HOST");
+    if (!codes_path) return fail(CASHASH_E_INVAL, "null codes path");
+    if (host_budget_bytes <= 0) return fail(CASHASH_E_INVAL, "host_budget_bytes must be > 0");
+    zero_stats(stats);
+    const double t0 = now_ms();
+    SetFile S;
+    RETCHK(open_set(set_path, S));
+    const int M = S.n_images;
+    const int64_t N = S.offs.back();
+    // groups: consecutive images, two resident (current + prefetched)
+    const int64_t slot = host_budget_bytes / 2;
+    std::vector<int> first{0};
+    int64_t fill = 0;
+    for (int m = 0; m < M; ++m) {
+        const int64_t b = (int64_t)S.n_feat[m] * kDim;
+        if (b > slot) return fail(CASHASH_E_NOMEM, "image %d does not fit a host group of %lld bytes", m, (long long)slot);
+        if (fill + b > slot && fill > 0) {
+            first.push_back(m);
+            fill = 0;
+        }
+        fill += b;
+    }
+    first.push_back(M);
+    const int ng = (int)first.size() - 1;
+    std::vector<uint8_t> buf[2];
+    buf[0].resize((size_t)std::max<int64_t>(slot, 1));
+    buf[1].resize((size_t)std::max<int64_t>(slot, 1));
+    int64_t disk = 0, group_loads = 0;
+    auto read_group = [&](int g, int s) -> bool {
+        const int64_t r0 = S.offs[first[g]], r1 = S.offs[first[g + 1]];
+        return read_at(S.f.fd, buf[s].data(), (size_t)(r1 - r0) * kDim, S.desc_off + r0 * kDim);
+    };
+    auto view = [&](int g, int s, std::vector<const uint8_t*>& dp, std::vector<int32_t>& nf) {
+        dp.clear();
+        nf.clear();
+        const int64_t r0 = S.offs[first[g]];
+        for (int m = first[g]; m < first[g + 1]; ++m) {
+            dp.push_back(buf[s].data() + (S.offs[m] - r0) * kDim);
+            nf.push_back(S.n_feat[m]);
+        }
+    };
+    Fd out;
+    out.fd = ::open(codes_path, O_RDWR | O_CREAT | O_TRUNC, 0644);
+    if (out.fd < 0) return fail(CASHASH_E_IO, "cannot create %s", codes_path);
+    const int64_t hdr[2] = {(int64_t)M, N};
+    if (!write_at(out.fd, kCodMagic, 8, 0) || !write_at(out.fd, hdr, 16, 8) ||
+        ::ftruncate(out.fd, (off_t)(kFileHeader + N * 22)) != 0)
+        return fail(CASHASH_E_IO, "write to %s failed", codes_path);
+    HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
+    HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
+    int64_t near = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        // first line: the group in progress; second line: the next group read ahead
+        if (ng > 0 && !read_group(0, 0)) return fail(CASHASH_E_IO, "read of %s failed", set_path);
+        group_loads += ng > 0;
+        for (int g = 0; g < ng; ++g) {
+            const int s = g & 1;
+            std::future<bool> ahead;
+            if (g + 1 < ng) ahead = std::async(std::launch::async, read_group, g + 1, s ^ 1);
+            std::vector<const uint8_t*> dp;
+            std::vector<int32_t> nf;
+            view(g, s, dp, nf);
+            cashash_images gi{(int32_t)nf.size(), dp.data(), nf.data()};
+            int rc;
+            if (pass == 0) {
+                rc = build_codes_host(c, &gi, nullptr, nullptr, &near, stats, kPassSums);
+            } else {
+                const int64_t r0 = S.offs[first[g]], r1 = S.offs[first[g + 1]];
+                std::vector<uint8_t> cb((size_t)(r1 - r0) * 22);
+                std::vector<uint64_t*> co;
+                std::vector<uint8_t*> ko;
+                for (int m = first[g]; m < first[g + 1]; ++m) {
+                    co.push_back(reinterpret_cast<uint64_t*>(cb.data() + (S.offs[m] - r0) * 16));
+                    ko.push_back(cb.data() + (r1 - r0) * 16 + (S.offs[m] - r0) * 6);
+                }
+                rc = build_codes_host(c, &gi, co.data(), ko.data(), &near, stats, kPassCodes, (double)N);
+                if (rc == CASHASH_OK &&
+                    (!write_at(out.fd, cb.data(), (size_t)(r1 - r0) * 16, kFileHeader + r0 * 16) ||
+                     !write_at(out.fd, cb.data() + (r1 - r0) * 16, (size_t)(r1 - r0) * 6, kFileHeader + N * 16 + r0 * 6)))
+                    rc = fail(CASHASH_E_IO, "write to %s failed", codes_path);
+            }
+            const bool read_ok = !ahead.valid() || ahead.get();
+            if (rc != CASHASH_OK) return rc;
+            if (!read_ok) return fail(CASHASH_E_IO, "read of %s failed", set_path);
+            disk += (S.offs[first[g + 1]] - S.offs[first[g]]) * kDim;
+            group_loads += g + 1 < ng;
+        }
+        if (pass == 0 && N > 0)
+            HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), (double)N,
+                               c->dBias.as<float>()));
+    }
+    if (::fdatasync(out.fd) != 0) return fail(CASHASH_E_IO, "sync of %s failed", codes_path);
+    if (stats) {
+        stats->near_margin_recomputes = near;
+        stats->disk_bytes = disk;
+        stats->group_loads = group_loads;
+        stats->ms_codes = now_ms() - t0;
+    }
+    return CASHASH_OK;
+}
+
+extern "C" int cashash_match_pairs_disk(cashash_ctx* c, const char* set_path, const char* codes_path,
+                                        int64_t n_pairs, const int32_t* pairs, const char* out_path,
+                                        const char* progress_path, int64_t host_budget_bytes, int64_t max_steps,
+                                        int64_t* steps_left, cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    if (c->cfg.mem != CASHASH_MEM_HOST) return fail(CASHASH_E_INVAL, "the disk level needs cfg.mem = CASHASH_MEM_HOST");
+    if (!codes_path || !out_path) return fail(CASHASH_E_INVAL, "null path");
+    if (host_budget_bytes <= 0) return fail(CASHASH_E_INVAL, "host_budget_bytes must be > 0");
+    if (max_steps < 0) return fail(CASHASH_E_INVAL, "max_steps must be >= 0");
+    zero_stats(stats);
+    const double t0 = now_ms();
+    SetFile S;
+    RETCHK(open_set(set_path, S));
+    const int M = S.n_images;
+    const int64_t N = S.offs.back();
+    RETCHK(check_pairs(M, n_pairs, pairs));
+    Fd cf;
+    cf.fd = ::open(codes_path, O_RDONLY);
+    if (cf.fd < 0) return fail(CASHASH_E_IO, "cannot open codes file %s", codes_path);
+    {
+        char magic[8];
+        int64_t hdr[2];
+        if (!read_at(cf.fd, magic, 8, 0) || std::memcmp(magic, kCodMagic, 8) != 0 || !read_at(cf.fd, hdr, 16, 8) ||
+            hdr[0] != M || hdr[1] != N)
+            return fail(CASHASH_E_IO, "%s is not the codes file of %s", codes_path, set_path);
+    }
+    // group pairs: the block-pair scheduler over images with host slots of a
+    // third of the budget (two groups in progress, one read ahead)
+    const int64_t slot = host_budget_bytes / 3;
+    std::vector<int64_t> img_bytes(M);
+    for (int m = 0; m < M; ++m) img_bytes[m] = (int64_t)S.n_feat[m] * (kDim + 22);
+    Schedule G;
+    const int pr = plan_schedule(M, img_bytes.data(), n_pairs, pairs, slot, G);
+    if (pr == -1) return fail(CASHASH_E_NOMEM, "an image does not fit a host group of %lld bytes", (long long)slot);
+    if (pr) return fail(CASHASH_E_INVAL, "scheduler rejected the pair list");
+    const int64_t n_steps = (int64_t)G.steps.size();
+    std::vector<int64_t> out_off(n_pairs);
+    int64_t T = 0;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        out_off[p] = T;
+        T += S.n_feat[pairs[2 * p]];
+    }
+    // output file (kept if it already has the right header: a resumed run)
+    Fd of;
+    of.fd = ::open(out_path, O_RDWR | O_CREAT, 0644);
+    if (of.fd < 0) return fail(CASHASH_E_IO, "cannot open %s", out_path);
+    {
+        const int64_t hdr[2] = {n_pairs, T};
+        char magic[8];
+        int64_t old[2] = {-1, -1};
+        struct stat st;
+        const bool same = ::fstat(of.fd, &st) == 0 && st.st_size == (off_t)(kFileHeader + 12 * T) &&
+                          read_at(of.fd, magic, 8, 0) && std::memcmp(magic, kOutMagic, 8) == 0 &&
+                          read_at(of.fd, old, 16, 8) && old[0] == n_pairs && old[1] == T;
+        if (!same && (::ftruncate(of.fd, 0) != 0 || ::ftruncate(of.fd, (off_t)(kFileHeader + 12 * T)) != 0 ||
+                      !write_at(of.fd, kOutMagic, 8, 0) || !write_at(of.fd, hdr, 16, 8)))
+            return fail(CASHASH_E_IO, "write to %s failed", out_path);
+    }
+    // progress: one byte per group pair, valid only for the same plan
+    uint64_t hash = 1469598103934665603ull;
+    hash = fnv1a(hash, S.offs.data(), S.offs.size() * 8);
+    hash = fnv1a(hash, pairs, (size_t)n_pairs * 8);
+    hash = fnv1a(hash, &slot, 8);
+    hash = fnv1a(hash, &n_steps, 8);
+    std::vector<uint8_t> done((size_t)n_steps, 0);
+    Fd pf;
+    if (progress_path) {
+        pf.fd = ::open(progress_path, O_RDWR | O_CREAT, 0644);
+        if (pf.fd < 0) return fail(CASHASH_E_IO, "cannot open %s", progress_path);
+        char magic[8];
+        uint64_t h = 0;
+        int64_t ns = -1;
+        const bool same = read_at(pf.fd, magic, 8, 0) && std::memcmp(magic, kPrgMagic, 8) == 0 &&
+                          read_at(pf.fd, &h, 8, 8) && read_at(pf.fd, &ns, 8, 16) && h == hash && ns == n_steps &&
+                          (n_steps == 0 || read_at(pf.fd, done.data(), (size_t)n_steps, kFileHeader));
+        if (!same) {
+            std::fill(done.begin(), done.end(), 0);
+            const int64_t zero = 0;
+            if (::ftruncate(pf.fd, 0) != 0 || !write_at(pf.fd, kPrgMagic, 8, 0) || !write_at(pf.fd, &hash, 8, 8) ||
+                !write_at(pf.fd, &n_steps, 8, 16) || !write_at(pf.fd, &zero, 8, 24) ||
+                (n_steps > 0 && !write_at(pf.fd, done.data(), (size_t)n_steps, kFileHeader)) || ::fdatasync(pf.fd) != 0)
+                return fail(CASHASH_E_IO, "write to %s failed", progress_path);
+        }
+    }
+    // three host slots of groups: descriptors, codes and keys of each image
+    std::vector<uint8_t> hbuf[3];
+    int slot_group[3] = {-1, -1, -1};
+    int64_t slot_used[3] = {-1, -1, -1};
+    std::vector<int64_t> place(M, -1);  // image -> offset in its slot
+    std::vector<int> slot_of_img(M, -1);
+    int64_t disk = 0, group_loads = 0;
+    auto read_group = [&](int g, int s) -> bool {
+        // called on the read-ahead thread for a slot nobody else touches
+        std::vector<uint8_t>& b = hbuf[s];
+        int64_t need = 0;
+        for (int i = G.block_first[g]; i < G.block_first[g + 1]; ++i) need += img_bytes[G.block_images[i]];
+        if ((int64_t)b.size() < need) b.resize((size_t)need);
+        int64_t off = 0;
+        for (int i = G.block_first[g]; i < G.block_first[g + 1]; ++i) {
+            const int m = G.block_images[i];
+            const int64_t n = S.n_feat[m], r0 = S.offs[m];
+            if (n > 0 && (!read_at(S.f.fd, b.data() + off, (size_t)n * kDim, S.desc_off + r0 * kDim) ||
+                          !read_at(cf.fd, b.data() + off + n * kDim, (size_t)n * 16, kFileHeader + r0 * 16) ||
+                          !read_at(cf.fd, b.data() + off + n * (kDim + 16), (size_t)n * 6, kFileHeader + N * 16 + r0 * 6)))
+                return false;
+            off += img_bytes[m];
+        }
+        return true;
+    };
+    auto bind_group = [&](int g, int s) {
+        int64_t off = 0;
+        for (int i = G.block_first[g]; i < G.block_first[g + 1]; ++i) {
+            const int m = G.block_images[i];
+            place[m] = off;
+            slot_of_img[m] = s;
+            off += img_bytes[m];
+        }
+        slot_group[s] = g;
+        disk += off;
+        group_loads++;
+    };
+    auto slot_holding = [&](int g) {
+        for (int s = 0; s < 3; ++s)
+            if (slot_group[s] == g) return s;
+        return -1;
+    };
+    auto free_slot = [&](int keep0, int keep1, int busy) {
+        int best = -1;
+        for (int s = 0; s < 3; ++s) {
+            if (s == busy || (slot_group[s] >= 0 && (slot_group[s] == keep0 || slot_group[s] == keep1))) continue;
+            if (best < 0 || slot_used[s] < slot_used[best]) best = s;
+        }
+        return best;
+    };
+    std::future<bool> ahead;
+    int ahead_group = -1, ahead_slot = -1;
+    auto finish_ahead = [&]() -> bool {
+        if (!ahead.valid()) return true;
+        const bool ok = ahead.get();
+        if (ok) bind_group(ahead_group, ahead_slot);
+        ahead_group = ahead_slot = -1;
+        return ok;
+    };
+    int64_t ran = 0;
+    cashash_stats st_step;
+    // outputs are written (and synced, then the progress byte) by a writer
+    // thread while the next group pair computes; two buffers alternate
+    std::vector<int32_t> o_bufs[2];
+    int cur = 0;
+    std::future<bool> writer;
+    int64_t writing = -1;  // group pair whose outputs the writer holds
+    auto finish_write = [&]() -> bool {
+        if (!writer.valid()) return true;
+        const bool ok = writer.get();
+        if (ok) done[writing] = 1;
+        writing = -1;
+        return ok;
+    };
+    for (int64_t st = 0; st < n_steps; ++st) {
+        if (done[st]) continue;
+        if (max_steps > 0 && ran >= max_steps) break;
+        const SchedStep& step = G.steps[st];
+        for (int g : {step.bi, step.bk}) {
+            if (slot_holding(g) >= 0) continue;
+            if (ahead_group == g) {
+                if (!finish_ahead()) return fail(CASHASH_E_IO, "read of %s or %s failed", set_path, codes_path);
+                continue;
+            }
+            if (!finish_ahead()) return fail(CASHASH_E_IO, "read of %s or %s failed", set_path, codes_path);
+            const int s = free_slot(step.bi, step.bk, -1);
+            slot_group[s] = -1;
+            if (!read_group(g, s)) return fail(CASHASH_E_IO, "read of %s or %s failed", set_path, codes_path);
+            bind_group(g, s);
+        }
+        const int si = slot_holding(step.bi), sk = slot_holding(step.bk);
+        slot_used[si] = slot_used[sk] = st;
+        // read ahead the next pending step's missing group
+        if (!ahead.valid())
+            for (int64_t nx = st + 1; nx < n_steps; ++nx) {
+                if (done[nx]) continue;
+                for (int g : {G.steps[nx].bi, G.steps[nx].bk}) {
+                    if (slot_holding(g) >= 0) continue;
+                    const int s = free_slot(step.bi, step.bk, -1);
+                    if (s < 0) break;
+                    slot_group[s] = -1;
+                    ahead_group = g;
+                    ahead_slot = s;
+                    ahead = std::async(std::launch::async, read_group, g, s);
+                    break;
+                }
+                break;
+            }
+        // host-memory matching of this group pair's pairs
+        std::vector<const uint8_t*> dp(M, nullptr), kp8(M, nullptr);
+        std::vector<const uint64_t*> cp(M, nullptr);
+        for (int g : {step.bi, step.bk})
+            for (int i = G.block_first[g]; i < G.block_first[g + 1]; ++i) {
+                const int m = G.block_images[i];
+                const uint8_t* base = hbuf[slot_of_img[m]].data() + place[m];
+                const int64_t n = S.n_feat[m];
+                dp[m] = base;
+                cp[m] = reinterpret_cast<const uint64_t*>(base + n * kDim);
+                kp8[m] = base + n * (kDim + 16);
+            }
+        cashash_images view{M, dp.data(), S.n_feat.data()};
+        MatchJob J;
+        int64_t nq = 0;
+        for (int64_t i = step.pair_begin; i < step.pair_end; ++i) {
+            const int64_t p = G.order[i];
+            J.pair_q.push_back(pairs[2 * p]);
+            J.pair_t.push_back(pairs[2 * p + 1]);
+            J.pair_out.push_back(nq);
+            nq += S.n_feat[pairs[2 * p]];
+        }
+        std::vector<int32_t>& o_buf = o_bufs[cur];
+        o_buf.assign((size_t)std::max<int64_t>(nq, 1) * 3, 0);
+        zero_stats(&st_step);
+        const int rc = match_host(c, &view, cp.data(), kp8.data(), nullptr, J, o_buf.data(), o_buf.data() + nq,
+                                  o_buf.data() + 2 * nq, &st_step);
+        if (rc != CASHASH_OK) {
+            finish_ahead();
+            finish_write();
+            return rc;
+        }
+        if (!finish_write()) {
+            finish_ahead();
+            return fail(CASHASH_E_IO, "write to %s or %s failed", out_path, progress_path ? progress_path : "");
+        }
+        writing = st;
+        writer = std::async(std::launch::async, [&, st, nq, b = cur, pb = step.pair_begin, pe = step.pair_end,
+                                                 po = std::move(J.pair_out)]() {
+            const std::vector<int32_t>& ob = o_bufs[b];
+            for (int64_t i = pb; i < pe; ++i) {
+                const int64_t p = G.order[i];
+                const int64_t n = S.n_feat[pairs[2 * p]];
+                for (int a = 0; n > 0 && a < 3; ++a)
+                    if (!write_at(of.fd, ob.data() + a * nq + po[i - pb], (size_t)n * 4,
+                                  kFileHeader + 4 * (a * T + out_off[p])))
+                        return false;
+            }
+            if (pf.fd >= 0) {
+                // durable outputs before the progress byte that vouches for them
+                const uint8_t one = 1;
+                if (::fdatasync(of.fd) != 0 || !write_at(pf.fd, &one, 1, kFileHeader + st) || ::fdatasync(pf.fd) != 0)
+                    return false;
+            }
+            return true;
+        });
+        cur ^= 1;
+        ++ran;
+        if (stats) {
+            stats->pairs += (int64_t)J.pair_q.size();
+            stats->queries += nq;
+            stats->bucket_entries += J.bucket_entries;
+            stats->union_size += J.union_size;
+            stats->ranked += J.ranked;
+            stats->h2d_bytes += st_step.h2d_bytes;
+            stats->d2h_bytes += st_step.d2h_bytes;
+            stats->image_loads += st_step.image_loads;
+        }
+    }
+    if (!finish_write()) {
+        finish_ahead();
+        return fail(CASHASH_E_IO, "write to %s or %s failed", out_path, progress_path ? progress_path : "");
+    }
+    if (!finish_ahead()) return fail(CASHASH_E_IO, "read of %s or %s failed", set_path, codes_path);
+    int64_t left = 0;
+    for (int64_t st = 0; st < n_steps; ++st) left += done[st] ? 0 : 1;
+    if (steps_left) *steps_left = left;
+    if (stats) {
+        stats->disk_bytes = disk;
+        stats->group_loads = group_loads;
+        stats->ms_match = now_ms() - t0;
+    }
     return CASHASH_OK;
 }
