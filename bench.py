@@ -36,9 +36,14 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "57cfcc4b7c22891d4e18c2dd240483033cd474d2fd9bd13cc34b1ec94be8a7f3",
+MEASURED_TRAFFIC = {"sources_sha256": "0244f5647f1c7e82061daed16d1b0df1d2f68477fa26197970ec9632e97995e6",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4673506.8 * 1024 * 2), "write_bytes": int(479179.0 * 1024)}
+                    "fetch_bytes": int(4586738.3 * 1024 * 2), "write_bytes": int(479167.8 * 1024),
+                    # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
+                    "valu_insts": 12729792872}
+# VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
+# every 4 cycles, 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def matcher_sha256():
@@ -54,6 +59,17 @@ def measured_traffic(workload):
     if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
+
+
+def measured_valu_issue(workload, kernel_ms):
+    """Counted VALU instructions of the matcher over what the SIMDs can issue
+    in its measured time (null once the sources changed)."""
+    t = MEASURED_TRAFFIC
+    if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
+        return None
+    return {"valu_insts": t["valu_insts"],
+            "frac": round(t["valu_insts"] / (VALU_ISSUE_PEAK * kernel_ms * 1e-3), 4),
+            "note": "SQ_INSTS_VALU of one launch / (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction x kernel time)"}
 
 
 def log(msg):
@@ -320,6 +336,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"),
                      "kernel": "match_kernel<false, 4>", "kernel_ms": round(kernel_ms, 4),
+                     "valu_issue": measured_valu_issue(
+                         f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs", kernel_ms),
                      "note": ("achieved = algorithmic (touched) bytes of the byte model / kernel time; "
                               "frac > 1 means the working set is re-read from L2/LDS (cache reuse); "
                               "traffic = measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)"),

@@ -171,6 +171,32 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_cofs[kWavesPerBlock][kMaxTile * 8];  // per query: C_0..C_5
+    // arguments needed only when work is grabbed or a tile is finished, kept
+    // in LDS rather than in scalar registers (the kernel is short of them)
+    struct Rare {
+        int32_t* o_idx;
+        int32_t* o_d1;
+        int32_t* o_d2;
+        unsigned long long* stats;
+        uint32_t* counter;
+        int64_t num2, den2;
+        int32_t seg[kSegments + 1];
+        int32_t grab;
+    };
+    __shared__ Rare s_rare;
+    if (threadIdx.x == 0) {
+        s_rare.o_idx = o_idx;
+        s_rare.o_d1 = o_d1;
+        s_rare.o_d2 = o_d2;
+        s_rare.stats = stats;
+        s_rare.counter = counter;
+        s_rare.num2 = prm.num2;
+        s_rare.den2 = prm.den2;
+        for (int i = 0; i <= kSegments; ++i) s_rare.seg[i] = prm.seg[i];
+        s_rare.grab = prm.grab;
+    }
+    __syncthreads();
+    const bool persistent = counter != nullptr;
     const int lane = threadIdx.x & 63;
     const int wv = (int)uniform(threadIdx.x >> 6);
     uint32_t* hist = s_hist[wv];
@@ -188,18 +214,19 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     int32_t it = (int32_t)(blockIdx.x * kWavesPerBlock + wv);
     int32_t cur = 0, end = 0;
     for (;;) {
-        if (counter) {
+        if (persistent) {
             if (cur >= end) {
                 for (int sx = 0; sx < kSegments; ++sx) {
                     const uint32_t x = (home + (uint32_t)sx) & (kSegments - 1);
-                    const int32_t s0 = prm.seg[x], s1 = prm.seg[x + 1];
+                    const int32_t s0 = s_rare.seg[x], s1 = s_rare.seg[x + 1];
                     if (s0 >= s1) continue;
                     uint32_t v = 0;
-                    if (lane == 0) v = atomicAdd(counter + x * kCounterStride, (uint32_t)prm.grab);
+                    const int32_t grab = s_rare.grab;
+                    if (lane == 0) v = atomicAdd(s_rare.counter + x * kCounterStride, (uint32_t)grab);
                     v = readlane(v, 0);
                     if ((int64_t)s0 + v < (int64_t)s1) {
                         cur = s0 + (int32_t)v;
-                        end = min(cur + prm.grab, s1);
+                        end = min(cur + grab, s1);
                         break;
                     }
                 }
@@ -264,8 +291,11 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 const uint16_t* kqq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * q);
                 qr.qk = (uint64_t)kqq[0] | ((uint64_t)kqq[1] << 16) | ((uint64_t)kqq[2] << 32);
             }
-            qr.P1 = readlane(v_P[0], qi); qr.P2 = readlane(v_P[1], qi); qr.P3 = readlane(v_P[2], qi);
-            qr.P4 = readlane(v_P[3], qi); qr.P5 = readlane(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
+            // run boundaries P1..P5 only meet per-lane compares: broadcast into
+            // vector registers (the kernel is short of scalar registers);
+            // P6 bounds the loops and stays scalar
+            qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
+            qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
             qr.cofs = cofs + 8 * qi;
             if constexpr (EPI) {
                 qr.la = readlane_f64(v_la, qi);
@@ -564,23 +594,23 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             if (my_kk >= 1) r_d1 = (int32_t)(best >> 32);
             if (my_kk >= 2) {
                 r_d2 = (int32_t)sec;
-                if (prm.den2 * (int64_t)r_d1 < prm.num2 * (int64_t)r_d2) r_idx = (int32_t)(uint32_t)best;
+                if (s_rare.den2 * (int64_t)r_d1 < s_rare.num2 * (int64_t)r_d2) r_idx = (int32_t)(uint32_t)best;
             }
             const int64_t o = pr.out + q0 + lane;
-            o_idx[o] = r_idx;
-            o_d1[o] = r_d1;
-            o_d2[o] = r_d2;
+            s_rare.o_idx[o] = r_idx;
+            s_rare.o_d1[o] = r_d1;
+            s_rare.o_d2[o] = r_d2;
         }
         wave_sync();
-        if (!counter) break;
+        if (!persistent) break;
     }
     // statistics: bucket entries and ranked counts (uniform), union sizes (per lane)
     uint64_t u64 = st_union;
     for (int d = 32; d >= 1; d >>= 1) u64 += __shfl_xor(u64, d);
-    if (lane == 0 && stats) {
-        atomicAdd(&stats[0], (unsigned long long)st_bucket);
-        atomicAdd(&stats[1], (unsigned long long)u64);
-        atomicAdd(&stats[2], (unsigned long long)st_ranked);
+    if (lane == 0 && s_rare.stats) {
+        atomicAdd(&s_rare.stats[0], (unsigned long long)st_bucket);
+        atomicAdd(&s_rare.stats[1], (unsigned long long)u64);
+        atomicAdd(&s_rare.stats[2], (unsigned long long)st_ranked);
     }
 }
 
