@@ -316,6 +316,12 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             uint32_t kr[NS];  // candidate keys held in registers (up to kRegCap)
 #pragma unroll
             for (int u = 0; u < NS; ++u) kr[u] = ~0u;
+            uint32_t n_slots = 0;  // register slots that hold candidates (the rest stay ~0u)
+            // the 8-slot kernel skips empty slots in the ranking loops; the
+            // 4-slot kernel keeps no slot count (its slots are nearly always
+            // full, and the count would take it past 80 VGPRs, the limit for
+            // six wavefronts per SIMD)
+            constexpr bool kSkipEmpty = NS > 4;
             bool in_regs = true;
             bool gathered = false;
             bool hist_built = true;  // false: the index table still has to be built from kr
@@ -344,6 +350,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 wave_sync();
                 if (n_surv <= kRegCap && n_surv <= (uint32_t)kListCap) {
                     const uint32_t slots = (n_surv + 63u) >> 6;
+                    n_slots = slots;
 #pragma unroll
                     for (int u = 0; u < NS; ++u) {
                         if ((uint32_t)u < slots) {
@@ -355,7 +362,8 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                         }
                     }
 #pragma unroll
-                    for (int u = 0; u < NS; ++u) n_valid += (uint32_t)__popcll(__ballot(kr[u] != ~0u));
+                    for (int u = 0; u < NS; ++u)
+                        if (!kSkipEmpty || (uint32_t)u < slots) n_valid += (uint32_t)__popcll(__ballot(kr[u] != ~0u));
                     gathered = true;  // the index table is built only if ranking is needed
                 }
                 wave_sync();
@@ -368,6 +376,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                     // common case: every bucket entry of the query fits the
                     // register slots; exactly ceil(total / 64) chunks are read
                     const uint32_t nch = (total + 63u) >> 6;
+                    n_slots = nch;
                     switch (nch) {
 #define GATHER_CASE(C)                                                                            \
     case C:                                                                                       \
@@ -414,10 +423,11 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                     in_regs = n_valid <= kRegCap && n_valid <= (uint32_t)kListCap;
                     wave_sync();
                     if (in_regs) {
+                        n_slots = (n_valid + 63u) >> 6;
 #pragma unroll
                         for (int u = 0; u < NS; ++u) {
                             const uint32_t e = 64u * u + lane;
-                            kr[u] = e < n_valid ? list[e] : ~0u;
+                            if (!kSkipEmpty || (uint32_t)u < n_slots) kr[u] = e < n_valid ? list[e] : ~0u;
                         }
                     }
                 }
@@ -438,7 +448,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     do {                                                                                              \
         c = 0;                                                                                        \
         if (in_regs) {                                                                                \
-            _Pragma("unroll") for (int u = 0; u < NS; ++u) c +=                                \
+            _Pragma("unroll") for (int u = 0; u < NS; ++u) if (!kSkipEmpty || (uint32_t)u < n_slots) c += \
                 (uint32_t)__popcll(__ballot(kr[u] >= (lo) && kr[u] < (hi)));                          \
         } else {                                                                                      \
             for (uint32_t base = 0; base < span; base += 64) {                                        \
@@ -458,7 +468,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                     clear_hist(hist, lane);
 #pragma unroll
                     for (int u = 0; u < NS; ++u)
-                        if (kr[u] != ~0u) atomicAdd(&hist[kr[u] >> 16], 1u);
+                        if ((!kSkipEmpty || (uint32_t)u < n_slots) && kr[u] != ~0u) atomicAdd(&hist[kr[u] >> 16], 1u);
                     wave_sync();
                 }
                 // ---- Step 3: Hamming distance H* of the kk-th candidate from the index table
@@ -476,6 +486,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                     if (in_regs) {
 #pragma unroll
                         for (int u = 0; u < NS; ++u) {
+                            if (kSkipEmpty && (uint32_t)u >= n_slots) break;
                             const bool tie = kr[u] >= lo && kr[u] < hi;
                             const uint64_t mk = __ballot(tie);
                             const uint32_t slot = nt + mbcnt64(mk);
@@ -518,6 +529,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             if (in_regs) {
 #pragma unroll
                 for (int u = 0; u < NS; ++u) {
+                    if (kSkipEmpty && (uint32_t)u >= n_slots) break;
                     const bool keep = kr[u] <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
