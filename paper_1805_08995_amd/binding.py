@@ -132,6 +132,15 @@ def default_config() -> Config:
     return c
 
 
+def _n_queries(images, pairs):
+    """Total queries of a pair list (the sum of its query images' sizes).
+    Out-of-range indices are clipped here and rejected by the library."""
+    if not len(pairs):
+        return 0
+    nf = np.fromiter((int(im.shape[0]) for im in images), np.int64, len(images))
+    return int(np.take(nf, pairs[:, 0], mode="clip").sum()) if len(nf) else 0
+
+
 def _ptrs(vals):
     return (C.c_void_p * max(1, len(vals)))(*vals)
 
@@ -256,7 +265,7 @@ class Matcher:
         """(match_idx, d1sq, d2sq), flat over pairs in pair order."""
         st, keep = self._images(images)
         pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
-        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if len(pairs) else 0
+        n = _n_queries(images, pairs)
         o = self._outputs(n, out)
         stats = Stats()
         check(lib().cashash_match_pairs(self.h, C.byref(st), self._arrays(codes), self._arrays(keys), len(pairs),
@@ -271,7 +280,7 @@ class Matcher:
         F = np.ascontiguousarray(F, np.float64).reshape(-1, 9)
         if len(F) != len(pairs):
             raise ValueError("one F per pair")
-        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if len(pairs) else 0
+        n = _n_queries(images, pairs)
         o = self._outputs(n, out)
         stats = Stats()
         check(lib().cashash_match_pairs_epipolar(
@@ -370,7 +379,7 @@ class Matcher:
         g.frac_num, g.frac_den, g.min_matches = int(frac[0]), int(frac[1]), int(min_matches)
         g.n_hyp, g.ransac_px, g.band_px, g.rand8 = len(r), float(ransac_px), float(band_px), r.ctypes.data
         P = len(pairs)
-        n = int(sum(int(images[q].shape[0]) for q in pairs[:, 0])) if P else 0
+        n = _n_queries(images, pairs)
         o = self._outputs(n, out)
         res = dict(F=np.zeros((P, 9)), n_matches=np.zeros(P, np.int32), n_inliers=np.zeros(P, np.int32),
                    status=np.zeros(P, np.int32))

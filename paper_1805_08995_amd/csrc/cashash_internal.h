@@ -15,7 +15,7 @@ constexpr int kRowTiles = kRows / 16;                   // 11 MFMA row tiles
 constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
 constexpr int kMaxK = 64;
 constexpr int kListCap = 512;      // per-wave LDS candidate list (u32 keys); reused for tile distances
-constexpr int kSelCap = 512;       // per-wave LDS list of a query tile's kept candidates
+constexpr int kSelCap = 384;       // per-wave LDS list of a query tile's kept candidates
 // A query's candidate keys are held in NS 64-wide register slots (NS = 4 or
 // 8, a template parameter of the matcher); queries with more candidates use
 // the LDS list.  Pairs whose train image has more than kLargeTrain points run

@@ -61,13 +61,25 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
     wave_sync();
 }
 
-// Per-query view of the six bucket runs: bucket start of table t (b0..b5) and
-// prefix sums of the bucket sizes (P1..P6), plus the query's code and keys and
-// its epipolar line.  Passed by value so every field stays in registers.
+// Per-query view of the six bucket runs concatenated in table order, plus the
+// query's code and keys and its epipolar line.  Passed by value so every
+// field stays in registers.  Two layouts of the run table qtab (LDS, per
+// query), both giving for candidate e its entry position e + C (C = t * n +
+// b_t - start of its run, of table t) and 8t (the shift that masks the keys
+// of tables >= t in the union test):
+//  by table (most kernels): P1..P5 are the run starts of tables 1..5 and P6
+//    the number of bucket entries; the number of starts at or below e is its
+//    table t, and qtab[t] = C.
+//  by ordinal (the 4-slot plain kernel): P1..P5 are the starts of the
+//    non-empty runs after the first non-empty one (~0u for the other runs),
+//    whose count at or below e is the ordinal o of e's run among the
+//    non-empty runs, and qtab[o] = (C << 6) | 8t.  qtab[8 + 2u .. 9 + 2u]
+//    holds the 64-bit mask of those starts inside chunk u (bit j: a start at
+//    candidate 64u + j + 1), so a lane finds its ordinal with mbcnt.
 struct QueryRuns {
     uint64_t qc0, qc1, qk;
     uint32_t P1, P2, P3, P4, P5, P6;
-    const uint32_t* cofs;  // LDS: C_t = t * n_t + b_t - P_t, candidate e of table t sits at entry e + C_t
+    const uint32_t* qtab;
     double la, lb, lc;
 };
 
@@ -85,12 +97,20 @@ struct TrainView {
 // loads are unconditional (a clamped position) so several calls can have
 // their loads in flight together.  n_union counts candidates that survive
 // the union and the band.
-// Table t and entry position of candidate e of the concatenated runs; lanes
-// past the runs get candidate 0's position (a valid address).
-__device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, uint32_t& t) {
+// Entry position of candidate e of the concatenated runs; cw receives 8t in
+// its low 6 bits.  Lanes past the runs get candidate 0's position (a valid
+// address).
+template <bool ORD>
+__device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, uint32_t& cw) {
     const uint32_t ec = e < r.P6 ? e : 0u;
-    t = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
-    return ec + r.cofs[t];
+    const uint32_t o = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
+    if constexpr (ORD) {
+        cw = r.qtab[o];
+        return ec + (cw >> 6);
+    } else {
+        cw = 8u * o;
+        return ec + r.qtab[o];
+    }
 }
 
 // Eq. 1-2: the candidate's keypoint lies within the band around the
@@ -102,19 +122,18 @@ __device__ __forceinline__ bool in_band(const TrainView& tv, uint32_t pos, const
     return ev * ev <= dd * (r.la * r.la + r.lb * r.lb);
 }
 
-// Entry (t, pos) -> packed key (Hamming << 16 | index), or ~0u if it repeats
-// an earlier table's candidate or exceeds tau.  `live` masks lanes with no
-// candidate; n_union counts candidates that survive the union.
-__device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t t, uint32_t pos, bool live,
-                                              const QueryRuns& r, int32_t tau, uint32_t& n_union) {
-    const ulonglong2 c = gload(tv.code + pos);
-    const uint64_t kid = gload(tv.kid + pos);
+// Loaded entry (code c, keys and index kid) of a run of table t -> packed
+// key (Hamming << 16 | index), or ~0u if it repeats an earlier table's
+// candidate or exceeds tau.  The low 6 bits of cw hold 8t.  `live` masks
+// lanes with no candidate; n_union counts candidates that survive the union.
+__device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint32_t cw, bool live,
+                                               const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     // union: drop the candidate if it shares an earlier table's key with the
     // query (it was already collected there): a zero byte among bytes
     // 0 .. t-1 of keys ^ query keys.  Bytes t.. are forced to 0xFF with
     // fm = ~0 << 8t, then the exact zero-byte test (v - 0x01..) & ~v & 0x80..
     // runs on bytes 0-3 and on byte 4 (table 4's key, only below t = 5).
-    const uint64_t fm = ~0ull << (8u * t);
+    const uint64_t fm = ~0ull << (cw & 63u);
     const uint32_t y = ((uint32_t)kid ^ (uint32_t)r.qk) | (uint32_t)fm;
     const uint32_t y4 = ((uint32_t)(kid >> 32) ^ (uint32_t)(r.qk >> 32)) | (uint32_t)(fm >> 32);
     const bool dup = (((y - 0x01010101u) & ~y) | ((y4 - 0x01010101u) & ~y4 & 0xFFu)) & 0x80808080u;
@@ -125,16 +144,22 @@ __device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t t, u
     return ok ? ((h << 16) | (uint32_t)(kid >> 48)) : ~0u;
 }
 
+// The same for the entry at pos, loaded here.
+__device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t cw, uint32_t pos, bool live,
+                                              const QueryRuns& r, int32_t tau, uint32_t& n_union) {
+    return loaded_key(gload(tv.code + pos), gload(tv.kid + pos), cw, live, r, tau, n_union);
+}
+
 // Candidate e of the concatenated six bucket runs -> packed key, or ~0u if e
 // is past the runs, outside the epipolar band, a repeat or above tau.
-template <bool EPI>
+template <bool EPI, bool ORD>
 __device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, const QueryRuns& r, int32_t tau,
                                            double dd, uint32_t& n_union) {
-    uint32_t t;
-    const uint32_t pos = entry_pos(e, r, t);
+    uint32_t cw;
+    const uint32_t pos = entry_pos<ORD>(e, r, cw);
     bool live = e < r.P6;
     if constexpr (EPI) live = live && in_band(tv, pos, r, dd);
-    return entry_key(tv, t, pos, live, r, tau, n_union);
+    return entry_key(tv, cw, pos, live, r, tau, n_union);
 }
 
 // The first C chunks of 64 candidates into register slots, all loads issued
@@ -143,7 +168,39 @@ template <bool EPI, int C, int NS>
 __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, const TrainView& tv, const QueryRuns& r,
                                               int32_t tau, double dd, uint32_t& n_union) {
 #pragma unroll
-    for (int u = 0; u < C; ++u) kr[u] = key_at<EPI>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
+    for (int u = 0; u < C; ++u) kr[u] = key_at<EPI, false>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
+}
+
+// The same for the plain form when the runs fit 256 candidates: the run
+// ordinal of chunk u's lanes comes from the chunk's start mask with mbcnt
+// (o0 = starts at or below 64u, carried from chunk to chunk), and only the
+// last chunk can hold lanes past the runs.  Positions of all C chunks are
+// found first so that their loads are in flight together.
+template <int C, int NS>
+__device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane, const TrainView& tv,
+                                                   const QueryRuns& r, int32_t tau, uint32_t& n_union) {
+    uint32_t cw[C], pos[C];
+    uint32_t o0 = 0;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        const uint2 sm = *reinterpret_cast<const uint2*>(r.qtab + 8 + 2 * u);
+        const uint32_t o = __builtin_amdgcn_mbcnt_hi(sm.y, __builtin_amdgcn_mbcnt_lo(sm.x, o0));
+        if (u + 1 < C) o0 += (uint32_t)__popc(sm.x) + (uint32_t)__popc(sm.y);
+        const uint32_t e = 64u * u + (uint32_t)lane;
+        const bool live = u + 1 < C || e < r.P6;
+        cw[u] = r.qtab[live ? o : 0u];
+        pos[u] = (live ? e : 0u) + (cw[u] >> 6);
+    }
+    ulonglong2 c[C];
+    uint64_t kid[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        c[u] = gload(tv.code + pos[u]);
+        kid[u] = gload(tv.kid + pos[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u)
+        kr[u] = loaded_key(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau, n_union);
 }
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
@@ -159,8 +216,13 @@ __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, cons
 //             4 lanes per pair with v_dot4_u32_u8; lane l then takes query l's
 //             distances, picks the nearest and second nearest and applies the
 //             ratio test, and the tile's outputs are stored coalesced.
+// Resident blocks per CU each instantiation is compiled for (4 waves per
+// block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
 template <bool EPI, int NS>
-__global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ imgs,
+constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 5 : 6) : (EPI ? 4 : 5);
+
+template <bool EPI, int NS>
+__global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(const ImgDev* __restrict__ imgs,
                                                     const PairDev* __restrict__ pairs,
                                                     const Item* __restrict__ items, int32_t n_items,
                                                     uint32_t* __restrict__ counter, MatchParams prm,
@@ -170,7 +232,10 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
     __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
-    __shared__ __attribute__((aligned(16))) uint32_t s_cofs[kWavesPerBlock][kMaxTile * 8];  // per query: C_0..C_5
+    // run words (and, in the 4-slot plain kernel, chunk start masks) per query
+    constexpr bool kMask = NS == 4 && !EPI;
+    constexpr int kQS = kMask ? 16 : 8;
+    __shared__ __attribute__((aligned(16))) uint32_t s_qtab[kWavesPerBlock][kMaxTile * kQS];
     // arguments needed only when work is grabbed or a tile is finished, kept
     // in LDS rather than in scalar registers (the kernel is short of them)
     struct Rare {
@@ -202,7 +267,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
     uint32_t* hist = s_hist[wv];
     uint32_t* list = s_list[wv];
     uint32_t* sel = s_sel[wv];
-    uint32_t* cofs = s_cofs[wv];
+    uint32_t* qtab = s_qtab[wv];
     const int part = lane & 3;
     uint64_t st_bucket = 0, st_ranked = 0;
     uint32_t st_union = 0;
@@ -252,22 +317,45 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
         const uint64_t v_qc0 = gload(Q.codes + 2 * lq), v_qc1 = gload(Q.codes + 2 * lq + 1);
         const uint16_t* kq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * lq);
         const uint64_t v_qk = (uint64_t)gload(kq) | ((uint64_t)gload(kq + 1) << 16) | ((uint64_t)gload(kq + 2) << 32);
+        // v_P[0..4]: the run starts P1..P5 (see QueryRuns); v_P[5]: bucket entries
         uint32_t v_P[kTables];
         {
-            uint32_t acc = 0, cu[kTables];
+            // the previous tile's readers are done (the finalize step ended with a wave sync)
+            uint32_t* qt = qtab + kQS * lane;
+            const bool own = lane < kMaxTile;
+            if constexpr (kMask) {
+                if (own) {
+                    reinterpret_cast<uint4*>(qt + 8)[0] = make_uint4(0u, 0u, 0u, 0u);
+                    reinterpret_cast<uint4*>(qt + 8)[1] = make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+            uint32_t acc = 0, cnt = 0, cu[kTables];  // entries and non-empty runs before table t
 #pragma unroll
             for (int t = 0; t < kTables; ++t) {
                 const uint32_t v = (uint32_t)((v_qk >> (8 * t)) & 0xFFu);
                 const uint32_t b = gload(T.off + t * kOffStride + v);
-                cu[t] = (uint32_t)t * (uint32_t)T.n + b - acc;  // entry of candidate e of table t: e + cu[t]
-                acc += gload(T.off + t * kOffStride + v + 1) - b;
-                v_P[t] = acc;
+                const uint32_t len = gload(T.off + t * kOffStride + v + 1) - b;
+                const uint32_t start = acc;
+                cu[t] = (uint32_t)t * (uint32_t)T.n + b - start;  // candidate e of run t: entry e + cu[t]
+                if constexpr (kMask) {
+                    if (t > 0) v_P[t - 1] = (len != 0 && cnt != 0) ? start : ~0u;
+                    if (len != 0) {
+                        if (own) qt[cnt] = (cu[t] << 6) | (8u * (uint32_t)t);
+                        if (own && cnt != 0 && start <= 256u)
+                            atomicOr(qt + 8 + ((start - 1u) >> 5), 1u << ((start - 1u) & 31u));
+                        ++cnt;
+                    }
+                } else if (t > 0) {
+                    v_P[t - 1] = start;
+                }
+                acc += len;
             }
-            // the previous tile's readers are done (the finalize step ended with a wave sync)
-            if (lane < kMaxTile) {
-                uint4* cw = reinterpret_cast<uint4*>(cofs + 8 * lane);
-                cw[0] = make_uint4(cu[0], cu[1], cu[2], cu[3]);
-                cw[1] = make_uint4(cu[4], cu[5], 0u, 0u);
+            v_P[kTables - 1] = acc;
+            if constexpr (!kMask) {
+                if (own) {
+                    reinterpret_cast<uint4*>(qt)[0] = make_uint4(cu[0], cu[1], cu[2], cu[3]);
+                    reinterpret_cast<uint4*>(qt)[1] = make_uint4(cu[4], cu[5], 0u, 0u);
+                }
             }
             wave_sync();
         }
@@ -296,7 +384,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             // P6 bounds the loops and stays scalar
             qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
             qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
-            qr.cofs = cofs + 8 * qi;
+            qr.qtab = qtab + kQS * qi;
             if constexpr (EPI) {
                 qr.la = readlane_f64(v_la, qi);
                 qr.lb = readlane_f64(v_lb, qi);
@@ -333,18 +421,18 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 // the LDS list and only they are read in full
                 uint32_t n_surv = 0;
                 for (uint32_t base = 0; base < total; base += 128) {
-                    uint32_t t0, t1;
+                    uint32_t w0, w1;
                     const uint32_t e0 = base + lane, e1 = base + 64u + lane;
-                    const uint32_t p0 = entry_pos(e0, qr, t0), p1 = entry_pos(e1, qr, t1);
+                    const uint32_t p0 = entry_pos<kMask>(e0, qr, w0), p1 = entry_pos<kMask>(e1, qr, w1);
                     const bool ok0 = e0 < total && in_band(tv, p0, qr, dd);
                     const bool ok1 = e1 < total && in_band(tv, p1, qr, dd);
                     const uint64_t m0 = __ballot(ok0);
                     const uint32_t s0 = n_surv + mbcnt64(m0);
-                    if (ok0 && s0 < (uint32_t)kListCap) list[s0] = (t0 << 24) | p0;
+                    if (ok0 && s0 < (uint32_t)kListCap) list[s0] = ((w0 & 63u) << 24) | p0;
                     n_surv += (uint32_t)__popcll(m0);
                     const uint64_t m1 = __ballot(ok1);
                     const uint32_t s1 = n_surv + mbcnt64(m1);
-                    if (ok1 && s1 < (uint32_t)kListCap) list[s1] = (t1 << 24) | p1;
+                    if (ok1 && s1 < (uint32_t)kListCap) list[s1] = ((w1 & 63u) << 24) | p1;
                     n_surv += (uint32_t)__popcll(m1);
                 }
                 wave_sync();
@@ -380,7 +468,8 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                     switch (nch) {
 #define GATHER_CASE(C)                                                                            \
     case C:                                                                                       \
-        if constexpr (C <= NS) gather_chunks<EPI, C, NS>(kr, lane, tv, qr, prm.tau, dd, st_union); \
+        if constexpr (C <= NS && kMask) gather_chunks_mask<C, NS>(kr, lane, tv, qr, prm.tau, st_union); \
+        else if constexpr (C <= NS) gather_chunks<EPI, C, NS>(kr, lane, tv, qr, prm.tau, dd, st_union); \
         break;
                         GATHER_CASE(1)
                         GATHER_CASE(2)
@@ -407,7 +496,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                         uint32_t kv[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            kv[u] = key_at<EPI>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+                            kv[u] = key_at<EPI, kMask>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const bool keep = kv[u] != ~0u;
@@ -454,7 +543,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
             for (uint32_t base = 0; base < span; base += 64) {                                        \
                 const uint32_t e = base + lane;                                                       \
                 const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)                          \
-                                             : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);            \
+                                             : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);            \
                 c += (uint32_t)__popcll(__ballot(key >= (lo) && key < (hi)));                         \
             }                                                                                         \
         }                                                                                             \
@@ -497,7 +586,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                         for (uint32_t base = 0; base < span; base += 64) {
                             const uint32_t e = base + lane;
                             const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                         : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
+                                                         : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);
                             const bool tie = key >= lo && key < hi;
                             const uint64_t mk = __ballot(tie);
                             const uint32_t slot = nt + mbcnt64(mk);
@@ -540,7 +629,7 @@ __global__ __launch_bounds__(256) void match_kernel(const ImgDev* __restrict__ i
                 for (uint32_t base = 0; base < span; base += 64) {
                     const uint32_t e = base + lane;
                     const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                 : key_at<EPI>(e, tv, qr, prm.tau, dd, dummy);
+                                                 : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);
                     const bool keep = key <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
