@@ -73,9 +73,10 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
 //  by ordinal (the 4-slot plain kernel): P1..P5 are the starts of the
 //    non-empty runs after the first non-empty one (~0u for the other runs),
 //    whose count at or below e is the ordinal o of e's run among the
-//    non-empty runs, and qtab[o] = (C << 6) | 8t.  qtab[8 + 2u .. 9 + 2u]
+//    non-empty runs, and qtab[o] = (16 C << 6) | 8t.  qtab[8 + 2u .. 9 + 2u]
 //    holds the 64-bit mask of those starts inside chunk u (bit j: a start at
-//    candidate 64u + j + 1), so a lane finds its ordinal with mbcnt.
+//    candidate 64u + j + 1), so a lane finds its ordinal with mbcnt, and
+//    bits 3(u-1) .. 3u-1 of qtab[6] count the starts at or below 64u.
 struct QueryRuns {
     uint64_t qc0, qc1, qk;
     uint32_t P1, P2, P3, P4, P5, P6;
@@ -106,7 +107,7 @@ __device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, ui
     const uint32_t o = (uint32_t)(ec >= r.P1) + (ec >= r.P2) + (ec >= r.P3) + (ec >= r.P4) + (ec >= r.P5);
     if constexpr (ORD) {
         cw = r.qtab[o];
-        return ec + (cw >> 6);
+        return ec + (cw >> 10);
     } else {
         cw = 8u * o;
         return ec + r.qtab[o];
@@ -122,10 +123,22 @@ __device__ __forceinline__ bool in_band(const TrainView& tv, uint32_t pos, const
     return ev * ev <= dd * (r.la * r.la + r.lb * r.lb);
 }
 
+// popcount(x) + acc as one v_bcnt_u32_b32 (a dependent chain keeps the
+// compiler from splitting a 128-bit count into two halves and an add).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // Loaded entry (code c, keys and index kid) of a run of table t -> packed
 // key (Hamming << 16 | index), or ~0u if it repeats an earlier table's
 // candidate or exceeds tau.  The low 6 bits of cw hold 8t.  `live` masks
 // lanes with no candidate; n_union counts candidates that survive the union.
+// CHAIN selects hand-picked instructions for the union test and a chained
+// count (the plain kernels); the band kernels, where few entries get here,
+// keep the compiler's own, which schedules better there.
+template <bool CHAIN>
 __device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint32_t cw, bool live,
                                                const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     // union: drop the candidate if it shares an earlier table's key with the
@@ -134,20 +147,40 @@ __device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint3
     // fm = ~0 << 8t, then the exact zero-byte test (v - 0x01..) & ~v & 0x80..
     // runs on bytes 0-3 and on byte 4 (table 4's key, only below t = 5).
     const uint64_t fm = ~0ull << (cw & 63u);
-    const uint32_t y = ((uint32_t)kid ^ (uint32_t)r.qk) | (uint32_t)fm;
-    const uint32_t y4 = ((uint32_t)(kid >> 32) ^ (uint32_t)(r.qk >> 32)) | (uint32_t)(fm >> 32);
-    const bool dup = (((y - 0x01010101u) & ~y) | ((y4 - 0x01010101u) & ~y4 & 0xFFu)) & 0x80808080u;
+    bool dup;
+    if constexpr (CHAIN) {
+        // bitop3 truth tables: 0xBE = (a ^ b) | c, 0x20 = a & ~b & c
+        const uint32_t y = __builtin_amdgcn_bitop3_b32((uint32_t)kid, (uint32_t)r.qk, (uint32_t)fm, 0xBE);
+        const uint32_t y4 =
+            __builtin_amdgcn_bitop3_b32((uint32_t)(kid >> 32), (uint32_t)(r.qk >> 32), (uint32_t)(fm >> 32), 0xBE);
+        const uint32_t zl = __builtin_amdgcn_bitop3_b32(y - 0x01010101u, y, 0x80808080u, 0x20);
+        const uint32_t zh = __builtin_amdgcn_bitop3_b32(y4 - 1u, y4, 0x80u, 0x20);
+        dup = (zl | zh) != 0u;
+    } else {
+        const uint32_t y = ((uint32_t)kid ^ (uint32_t)r.qk) | (uint32_t)fm;
+        const uint32_t y4 = ((uint32_t)(kid >> 32) ^ (uint32_t)(r.qk >> 32)) | (uint32_t)(fm >> 32);
+        dup = (((y - 0x01010101u) & ~y) | ((y4 - 0x01010101u) & ~y4 & 0xFFu)) & 0x80808080u;
+    }
     bool ok = live && !dup;
     n_union += ok ? 1u : 0u;
-    const uint32_t h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
+    uint32_t h;
+    if constexpr (CHAIN) {
+        h = (uint32_t)__popc((uint32_t)c.x ^ (uint32_t)r.qc0);
+        h = bcnt_acc((uint32_t)(c.x >> 32) ^ (uint32_t)(r.qc0 >> 32), h);
+        h = bcnt_acc((uint32_t)c.y ^ (uint32_t)r.qc1, h);
+        h = bcnt_acc((uint32_t)(c.y >> 32) ^ (uint32_t)(r.qc1 >> 32), h);
+    } else {
+        h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
+    }
     ok = ok && (int32_t)h <= tau;
     return ok ? ((h << 16) | (uint32_t)(kid >> 48)) : ~0u;
 }
 
 // The same for the entry at pos, loaded here.
+template <bool CHAIN>
 __device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t cw, uint32_t pos, bool live,
                                               const QueryRuns& r, int32_t tau, uint32_t& n_union) {
-    return loaded_key(gload(tv.code + pos), gload(tv.kid + pos), cw, live, r, tau, n_union);
+    return loaded_key<CHAIN>(gload(tv.code + pos), gload(tv.kid + pos), cw, live, r, tau, n_union);
 }
 
 // Candidate e of the concatenated six bucket runs -> packed key, or ~0u if e
@@ -159,7 +192,7 @@ __device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, cons
     const uint32_t pos = entry_pos<ORD>(e, r, cw);
     bool live = e < r.P6;
     if constexpr (EPI) live = live && in_band(tv, pos, r, dd);
-    return entry_key(tv, cw, pos, live, r, tau, n_union);
+    return entry_key<!EPI>(tv, cw, pos, live, r, tau, n_union);
 }
 
 // The first C chunks of 64 candidates into register slots, all loads issued
@@ -179,28 +212,28 @@ __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, cons
 template <int C, int NS>
 __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane, const TrainView& tv,
                                                    const QueryRuns& r, int32_t tau, uint32_t& n_union) {
-    uint32_t cw[C], pos[C];
-    uint32_t o0 = 0;
+    uint32_t cw[C], boff[C];  // run word; byte offset of the entry's code (16 bytes per entry)
+    const uint32_t pre = C > 1 ? r.qtab[6] : 0u;
 #pragma unroll
     for (int u = 0; u < C; ++u) {
         const uint2 sm = *reinterpret_cast<const uint2*>(r.qtab + 8 + 2 * u);
+        const uint32_t o0 = u == 0 ? 0u : (pre >> (3 * (u - 1))) & 7u;
         const uint32_t o = __builtin_amdgcn_mbcnt_hi(sm.y, __builtin_amdgcn_mbcnt_lo(sm.x, o0));
-        if (u + 1 < C) o0 += (uint32_t)__popc(sm.x) + (uint32_t)__popc(sm.y);
         const uint32_t e = 64u * u + (uint32_t)lane;
         const bool live = u + 1 < C || e < r.P6;
         cw[u] = r.qtab[live ? o : 0u];
-        pos[u] = (live ? e : 0u) + (cw[u] >> 6);
+        boff[u] = (cw[u] >> 6) + (live ? e << 4 : 0u);
     }
     ulonglong2 c[C];
     uint64_t kid[C];
 #pragma unroll
     for (int u = 0; u < C; ++u) {
-        c[u] = gload(tv.code + pos[u]);
-        kid[u] = gload(tv.kid + pos[u]);
+        c[u] = gload(reinterpret_cast<const ulonglong2*>(reinterpret_cast<const char*>(tv.code) + boff[u]));
+        kid[u] = gload(reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(tv.kid) + (boff[u] >> 1)));
     }
 #pragma unroll
     for (int u = 0; u < C; ++u)
-        kr[u] = loaded_key(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau, n_union);
+        kr[u] = loaded_key<true>(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau, n_union);
 }
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
@@ -330,6 +363,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 }
             }
             uint32_t acc = 0, cnt = 0, cu[kTables];  // entries and non-empty runs before table t
+            uint32_t pre = 0;                         // run starts at or below 64, 128, 192 (3 bits each)
 #pragma unroll
             for (int t = 0; t < kTables; ++t) {
                 const uint32_t v = (uint32_t)((v_qk >> (8 * t)) & 0xFFu);
@@ -340,9 +374,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 if constexpr (kMask) {
                     if (t > 0) v_P[t - 1] = (len != 0 && cnt != 0) ? start : ~0u;
                     if (len != 0) {
-                        if (own) qt[cnt] = (cu[t] << 6) | (8u * (uint32_t)t);
+                        if (own) qt[cnt] = (cu[t] << 10) | (8u * (uint32_t)t);
                         if (own && cnt != 0 && start <= 256u)
                             atomicOr(qt + 8 + ((start - 1u) >> 5), 1u << ((start - 1u) & 31u));
+                        if (cnt != 0)
+                            pre += (uint32_t)(start <= 64u) + ((uint32_t)(start <= 128u) << 3) +
+                                   ((uint32_t)(start <= 192u) << 6);
                         ++cnt;
                     }
                 } else if (t > 0) {
@@ -356,6 +393,8 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     reinterpret_cast<uint4*>(qt)[0] = make_uint4(cu[0], cu[1], cu[2], cu[3]);
                     reinterpret_cast<uint4*>(qt)[1] = make_uint4(cu[4], cu[5], 0u, 0u);
                 }
+            } else if (own) {
+                qt[6] = pre;
             }
             wave_sync();
         }
@@ -445,7 +484,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                             const uint32_t i = 64u * u + lane;
                             const bool live = i < n_surv;
                             const uint32_t packed = live ? list[i] : 0u;
-                            kr[u] = entry_key(tv, packed >> 24, live ? (packed & 0xFFFFFFu) : 0u, live, qr, prm.tau,
+                            kr[u] = entry_key<false>(tv, packed >> 24, live ? (packed & 0xFFFFFFu) : 0u, live, qr, prm.tau,
                                               st_union);
                         }
                     }
