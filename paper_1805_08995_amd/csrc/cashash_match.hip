@@ -42,18 +42,55 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 __device__ __forceinline__ double readlane_f64(double v, int l) { return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), l)); }
 
 // Smallest bin d of the 256-bin LDS index table whose cumulative count
-// reaches `need` (1 <= need <= total); *below = count in bins < d.
-__device__ __forceinline__ uint32_t hist_select(const uint32_t* hist, uint32_t need, int lane, uint32_t* below) {
+// reaches `need` (1 <= need <= total); *below = count in bins < d, *in_bin =
+// count in bin d.  Lane l holds bins 4l .. 4l+3.  READOUT (the plain
+// kernels): after the scan only the lane that crosses `need` is read out
+// (readlane) and the bin inside it is picked with scalar arithmetic; else
+// every lane picks its candidate bin and the crossing lane's is read (the
+// band kernels, which rarely rank and schedule better with this form).
+template <bool READOUT>
+__device__ __forceinline__ uint32_t hist_select(const uint32_t* hist, uint32_t need, int lane, uint32_t* below,
+                                                uint32_t* in_bin) {
     const uint4 h = reinterpret_cast<const uint4*>(hist)[lane];
-    const uint32_t s0 = h.x, s1 = s0 + h.y, s2 = s1 + h.z, s3 = s2 + h.w;
-    const uint32_t incl = wave_scan_dpp(s3);
-    const uint32_t ex = incl - s3;
-    const uint32_t i = (ex + s0 >= need) ? 0u : (ex + s1 >= need) ? 1u : (ex + s2 >= need) ? 2u : 3u;
-    const uint32_t bl = ex + (i == 0 ? 0u : i == 1 ? s0 : i == 2 ? s1 : s2);
-    const uint64_t m = __ballot(incl >= need);
-    const int L = __ffsll((unsigned long long)m) - 1;
-    *below = readlane(bl, L);
-    return readlane(4u * (uint32_t)lane + i, L);
+    if constexpr (READOUT) {
+        const uint32_t s3 = h.x + h.y + h.z + h.w;
+        const uint32_t incl = wave_scan_dpp(s3);
+        const uint64_t m = __ballot(incl >= need);
+        const int L = __ffsll((unsigned long long)m) - 1;
+        uint32_t b = readlane(incl - s3, L);
+        const uint32_t c0 = readlane(h.x, L), c1 = readlane(h.y, L), c2 = readlane(h.z, L), c3 = readlane(h.w, L);
+        uint32_t d = 4u * (uint32_t)L, c = c0;
+        if (b + c0 < need) {
+            b += c0;
+            ++d;
+            c = c1;
+            if (b + c1 < need) {
+                b += c1;
+                ++d;
+                c = c2;
+                if (b + c2 < need) {
+                    b += c2;
+                    ++d;
+                    c = c3;
+                }
+            }
+        }
+        *below = b;
+        *in_bin = c;
+        return d;
+    } else {
+        const uint32_t s0 = h.x, s1 = s0 + h.y, s2 = s1 + h.z, s3 = s2 + h.w;
+        const uint32_t incl = wave_scan_dpp(s3);
+        const uint32_t ex = incl - s3;
+        const uint32_t i = (ex + s0 >= need) ? 0u : (ex + s1 >= need) ? 1u : (ex + s2 >= need) ? 2u : 3u;
+        const uint32_t bl = ex + (i == 0 ? 0u : i == 1 ? s0 : i == 2 ? s1 : s2);
+        const uint64_t m = __ballot(incl >= need);
+        const int L = __ffsll((unsigned long long)m) - 1;
+        *below = readlane(bl, L);
+        const uint32_t d = readlane(4u * (uint32_t)lane + i, L);
+        *in_bin = readlane(hist[d], 0);
+        return d;
+    }
 }
 
 __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
@@ -526,8 +563,8 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     for (int u = 0; u < NS; ++u) {
                         if ((uint32_t)u < nch) {
                             const bool keep = kr[u] != ~0u;
-                            if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
                             n_valid += (uint32_t)__popcll(__ballot(keep));
+                            if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
                         }
                     }
                 } else {
@@ -601,9 +638,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 }
                 // ---- Step 3: Hamming distance H* of the kk-th candidate from the index table
                 uint32_t below;
-                const uint32_t hs = hist_select(hist, kk, lane, &below);
+                uint32_t ties;  // candidates at Hamming distance H*
+                const uint32_t hs = hist_select<!EPI>(hist, kk, lane, &below, &ties);
                 const uint32_t need = kk - below;
-                const uint32_t ties = readlane(hist[hs], 0);
                 if (ties == need) {
                     tkey = ((hs + 1u) << 16) - 1u;
                 } else if (ties <= 64) {
@@ -617,8 +654,10 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                             if (kSkipEmpty && (uint32_t)u >= n_slots) break;
                             const bool tie = kr[u] >= lo && kr[u] < hi;
                             const uint64_t mk = __ballot(tie);
+                            // the index table counted exactly these keys: nt < ties <= 64
+                            // (the band kernels keep a guard; their code schedules better with it)
                             const uint32_t slot = nt + mbcnt64(mk);
-                            if (tie && slot < 256u) hist[slot] = kr[u] & 0xFFFFu;
+                            if (tie && (!EPI || slot < 256u)) hist[slot] = kr[u] & 0xFFFFu;
                             nt += (uint32_t)__popcll(mk);
                         }
                     } else {
@@ -658,10 +697,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
 #pragma unroll
                 for (int u = 0; u < NS; ++u) {
                     if (kSkipEmpty && (uint32_t)u >= n_slots) break;
+                    // exactly kk <= k keys are kept per query and the host sizes
+                    // tiles so that nq * k <= kSelCap: the slot is in range
                     const bool keep = kr[u] <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
-                    if (keep && slot < (uint32_t)kSelCap) sel[slot] = ((uint32_t)qi << 16) | (kr[u] & 0xFFFFu);
+                    if (keep && (!EPI || slot < (uint32_t)kSelCap)) sel[slot] = ((uint32_t)qi << 16) | (kr[u] & 0xFFFFu);
                     sel_n += (uint32_t)__popcll(mk);
                 }
             } else {
