@@ -114,6 +114,8 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
 //    holds the 64-bit mask of those starts inside chunk u (bit j: a start at
 //    candidate 64u + j + 1), so a lane finds its ordinal with mbcnt, and
 //    bits 3(u-1) .. 3u-1 of qtab[6] count the starts at or below 64u.
+// In both, the query's key bytes 0-3 sit in qtab[7] and bytes 4-5 in bits
+// 16-31 of qtab[6].
 struct QueryRuns {
     uint64_t qc0, qc1, qk;
     uint32_t P1, P2, P3, P4, P5, P6;
@@ -425,13 +427,15 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 acc += len;
             }
             v_P[kTables - 1] = acc;
+            // the query's keys: bytes 0-3 in qt[7], bytes 4-5 in the high half of qt[6]
+            const uint32_t khi = (uint32_t)(v_qk >> 32) << 16;
             if constexpr (!kMask) {
                 if (own) {
                     reinterpret_cast<uint4*>(qt)[0] = make_uint4(cu[0], cu[1], cu[2], cu[3]);
-                    reinterpret_cast<uint4*>(qt)[1] = make_uint4(cu[4], cu[5], 0u, 0u);
+                    reinterpret_cast<uint4*>(qt)[1] = make_uint4(cu[4], cu[5], khi, (uint32_t)v_qk);
                 }
             } else if (own) {
-                qt[6] = pre;
+                reinterpret_cast<uint2*>(qt + 6)[0] = make_uint2(pre | khi, (uint32_t)v_qk);
             }
             wave_sync();
         }
@@ -448,12 +452,13 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
         for (int qi = 0; qi < nq; ++qi) {
             QueryRuns qr;
             {
-                // the query's code and keys: wave-uniform addresses, scalar loads
+                // the query's code (a wave-uniform address); its keys: from
+                // the run table, where the tile setup left them
                 const int64_t q = (int64_t)q0 + qi;
                 qr.qc0 = Q.codes[2 * q];
                 qr.qc1 = Q.codes[2 * q + 1];
-                const uint16_t* kqq = reinterpret_cast<const uint16_t*>(Q.keys + 6 * q);
-                qr.qk = (uint64_t)kqq[0] | ((uint64_t)kqq[1] << 16) | ((uint64_t)kqq[2] << 32);
+                const uint2 kw = *reinterpret_cast<const uint2*>(qtab + kQS * qi + 6);
+                qr.qk = (uint64_t)kw.y | ((uint64_t)(kw.x >> 16) << 32);
             }
             // run boundaries P1..P5 only meet per-lane compares: broadcast into
             // vector registers (the kernel is short of scalar registers);
