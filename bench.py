@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "145acf580e42a9af45af8989b930f2b42fbfe89cc5f7fe4a4a025f3e94a1036e",
+MEASURED_TRAFFIC = {"sources_sha256": "405148e5360302cce43f7782192c658ecaca4ee7eecdf403036e0f5e70b1378f",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4295810.2 * 1024 * 2), "write_bytes": int(479126.7 * 1024),
+                    "fetch_bytes": int(4377288.2 * 1024 * 2), "write_bytes": int(479161.3 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9678378952}
+                    "valu_insts": 9756390031}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

@@ -449,14 +449,26 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
         uint32_t my_kk = 0, my_off = 0, sel_n = 0;
         const uint32_t jbits = tv.n > 1 ? 32u - (uint32_t)__clz(tv.n - 1) : 0u;
 
+        // plain kernels: the next query's code (a wave-uniform address) is
+        // loaded while the current query is ranked
+        uint64_t nc0 = 0, nc1 = 0;
+        if constexpr (!EPI) {
+            nc0 = Q.codes[2 * (int64_t)q0];
+            nc1 = Q.codes[2 * (int64_t)q0 + 1];
+        }
         for (int qi = 0; qi < nq; ++qi) {
             QueryRuns qr;
             {
-                // the query's code (a wave-uniform address); its keys: from
-                // the run table, where the tile setup left them
-                const int64_t q = (int64_t)q0 + qi;
-                qr.qc0 = Q.codes[2 * q];
-                qr.qc1 = Q.codes[2 * q + 1];
+                // the query's code; its keys: from the run table, where the
+                // tile setup left them
+                if constexpr (EPI) {
+                    const int64_t q = (int64_t)q0 + qi;
+                    qr.qc0 = Q.codes[2 * q];
+                    qr.qc1 = Q.codes[2 * q + 1];
+                } else {
+                    qr.qc0 = nc0;
+                    qr.qc1 = nc1;
+                }
                 const uint2 kw = *reinterpret_cast<const uint2*>(qtab + kQS * qi + 6);
                 qr.qk = (uint64_t)kw.y | ((uint64_t)(kw.x >> 16) << 32);
             }
@@ -603,6 +615,11 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 }
             }
             wave_sync();
+            if constexpr (!EPI) {
+                const int64_t qn = (int64_t)q0 + min(qi + 1, nq - 1);
+                nc0 = Q.codes[2 * qn];
+                nc1 = Q.codes[2 * qn + 1];
+            }
             const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
             st_ranked += kk;
             if (lane == qi) {
