@@ -132,12 +132,37 @@ def default_config() -> Config:
     return c
 
 
+class Bound:
+    """A list of buffers of one kind (images, codes, keys, keypoints, ...)
+    marshalled once: the pointer array the library takes and the row counts.
+    For repeated calls on the same buffers (Matcher.bind); the buffers are
+    held here and must not be resized or moved while it is in use."""
+
+    def __init__(self, arrs, ptrs, n):
+        self.arrs, self.ptrs, self.n = arrs, ptrs, n
+
+    def __len__(self):
+        return len(self.arrs)
+
+    def __getitem__(self, i):
+        return self.arrs[i]
+
+    def __iter__(self):
+        return iter(self.arrs)
+
+
+def _rows(arrs):
+    if isinstance(arrs, Bound):
+        return arrs.n
+    return np.fromiter((int(a.shape[0]) for a in arrs), np.int32, len(arrs))
+
+
 def _n_queries(images, pairs):
     """Total queries of a pair list (the sum of its query images' sizes).
     Out-of-range indices are clipped here and rejected by the library."""
     if not len(pairs):
         return 0
-    nf = np.fromiter((int(im.shape[0]) for im in images), np.int64, len(images))
+    nf = _rows(images).astype(np.int64)
     return int(np.take(nf, pairs[:, 0], mode="clip").sum()) if len(nf) else 0
 
 
@@ -219,17 +244,30 @@ class Matcher:
         return ms.value, n.value
 
     # ------------------------------------------------------------ marshalling
+    def bind(self, arrs, dtype=None):
+        """Marshal a list of buffers once for repeated calls (see Bound).  In
+        host mode the arrays are made contiguous (dtype if given) first."""
+        arrs = list(arrs)
+        if self.mem != "device":
+            arrs = [np.ascontiguousarray(a, dtype) if dtype is not None else np.ascontiguousarray(a) for a in arrs]
+        return Bound(arrs, self._arrays(arrs), _rows(arrs))
+
     def _images(self, images):
-        nf = np.array([int(im.shape[0]) for im in images], np.int32)
-        if self.mem == "device":
-            ptrs = _ptrs([_dptr(im) for im in images])
+        if isinstance(images, Bound):
+            ptrs, nf = images.ptrs, images.n
         else:
-            images = [np.ascontiguousarray(im, np.uint8) for im in images]
-            ptrs = _ptrs([im.ctypes.data if im.size else None for im in images])
+            nf = _rows(images)
+            if self.mem == "device":
+                ptrs = _ptrs([_dptr(im) for im in images])
+            else:
+                images = [np.ascontiguousarray(im, np.uint8) for im in images]
+                ptrs = _ptrs([im.ctypes.data if im.size else None for im in images])
         st = Images(len(images), C.cast(ptrs, C.POINTER(C.c_void_p)), nf.ctypes.data_as(C.POINTER(C.c_int32)))
         return st, (ptrs, nf, images)
 
     def _arrays(self, arrs):
+        if isinstance(arrs, Bound):
+            return arrs.ptrs
         if self.mem == "device":
             return _ptrs([_dptr(a) for a in arrs])
         return _ptrs([a.ctypes.data if a.size else None for a in arrs])

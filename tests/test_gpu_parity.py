@@ -246,6 +246,33 @@ def test_match_deterministic_repeat(mats):
             assert np.array_equal(x, y.cpu().numpy())
 
 
+def test_bound_buffer_lists(mats):
+    """Buffer lists marshalled once (Matcher.bind) give the same codes and
+    matches as plain lists, in device and host mode, over repeated calls."""
+    w = synth.scene_set(seed=12, n_images=6, n_feat=1800, n_scenes=2)
+    imgs = list(w.images)
+    imgs[2] = imgs[2][:0]  # an empty image
+    oc, ok = oracle.build_codes(imgs, *mats)
+    exp = _oracle_all(imgs, oc, ok, w.pairs, k=10)
+    m = binding.Matcher(*mats)
+    dimgs = _dev(imgs)
+    codes = [torch.empty((len(a), 2), dtype=torch.int64, device="cuda") for a in imgs]
+    keys = [torch.empty((len(a), 6), dtype=torch.uint8, device="cuda") for a in imgs]
+    bi, bc, bk = m.bind(dimgs), m.bind(codes), m.bind(keys)
+    n = sum(len(imgs[q]) for q in w.pairs[:, 0])
+    outs = tuple(torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(3))
+    for rep in range(2):
+        c, k, _ = m.build_codes(bi, out=(bc, bk))
+        _assert_codes(codes, keys, oc, ok, f"bound codes {rep}")
+        got, _ = m.match_pairs(bi, c, k, w.pairs, out=outs)
+        _assert_match(got, exp, f"bound device {rep}")
+    mh = binding.Matcher(*mats, mem="host", device_budget_bytes=4_000_000)
+    hb = mh.bind(imgs, np.uint8)
+    hc, hk, _ = mh.build_codes(hb)
+    got, _ = mh.match_pairs(hb, mh.bind(hc), mh.bind(hk), w.pairs)
+    _assert_match(got, exp, "bound host")
+
+
 # ------------------------------------------------------------------ epipolar
 
 def test_epipolar_small_set(mats):
