@@ -455,9 +455,11 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     const bool mfma = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     // near list: one segment per projection wavefront, each large enough for
     // every descriptor that wavefront handles; per-segment counts in front
-    const int grid = mfma ? std::max(1, std::min((nt + 3) / 4, c->n_cu * 8)) : (int)(((int64_t)nt * 16 + 255) / 256);
+    // (MFMA form: a wavefront takes groups of kProjTB tiles, kProjTB * 16 descriptors)
+    const int groups = (nt + kProjTB - 1) / kProjTB;
+    const int grid = mfma ? std::max(1, std::min((groups + 3) / 4, c->n_cu * 8)) : (int)(((int64_t)nt * 16 + 255) / 256);
     const uint32_t n_seg = (uint32_t)grid * 4;
-    const uint32_t seg_cap = mfma ? (uint32_t)((nt + n_seg - 1) / n_seg) * 16 : 64;
+    const uint32_t seg_cap = mfma ? (uint32_t)((groups + n_seg - 1) / n_seg) * kProjTB * 16 : 64;
     const size_t count_bytes = al256((size_t)n_seg * 4);
     RETCHK(c->near.ensure(count_bytes + (size_t)n_seg * seg_cap * sizeof(NearEntry)));
     uint32_t* seg_count = c->near.as<uint32_t>();
@@ -804,13 +806,17 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     // batched: items ordered by train image, so the waves running together
     // share one train image's tables in L2
     P.order.resize(n_pairs);
-    std::iota(P.order.begin(), P.order.end(), 0);
     const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
-    if (batched)
-        std::stable_sort(P.order.begin(), P.order.end(), [&](int64_t a, int64_t b) {
-            const int sa = slots_for(J, a), sb = slots_for(J, b);
-            return sa != sb ? sa < sb : J.pair_t[a] < J.pair_t[b];
-        });
+    if (batched) {
+        // stable counting sort by (register-slot group, train image)
+        std::vector<int64_t> start((size_t)2 * n_img + 1, 0);
+        auto bucket = [&](int64_t p) { return (slots_for(J, p) == 8 ? n_img : 0) + J.pair_t[p]; };
+        for (int64_t p = 0; p < n_pairs; ++p) start[(size_t)bucket(p) + 1]++;
+        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+        for (int64_t p = 0; p < n_pairs; ++p) P.order[(size_t)start[(size_t)bucket(p)]++] = p;
+    } else {
+        std::iota(P.order.begin(), P.order.end(), 0);
+    }
     // launch shapes: cached, tuned now, or the default
     tune_cache_load(c);
     const std::string key = tune_key(batched, J.epi, c->cfg.k, n_pairs ? sum_nt / n_pairs : 0.0,

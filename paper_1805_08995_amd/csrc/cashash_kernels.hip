@@ -139,10 +139,12 @@ __device__ __forceinline__ void store_code(const CodeOut& o, int img, int row, b
     cnt += (uint32_t)__popcll(fm);
 }
 
-// BF16 hi+lo split on MFMA.  One wave per tile of 16 descriptors: for each of
-// the 11 row tiles, D[16 rows][16 desc] = sum over 4 k-steps of
-// (R_hi + R_lo)[rows][32 k] x X^T[32 k][desc] with v_mfma_f32_16x16x32_bf16.
-// Lane l holds descriptor l % 16 and rows 4 (l / 16) .. +3 of each row tile.
+// BF16 hi+lo split on MFMA.  One wave per group of kProjTB tiles of 16
+// descriptors: for each of the 11 row tiles, D[16 rows][16 desc] = sum over
+// 4 k-steps of (R_hi + R_lo)[rows][32 k] x X^T[32 k][desc] with
+// v_mfma_f32_16x16x32_bf16.  Each fragment of R is loaded once per group and
+// applied to every tile of it.  Lane l holds descriptor l % 16 of each tile
+// and rows 4 (l / 16) .. +3 of each row tile.
 __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict__ imgs,
                                                         const CodeOut* __restrict__ outs,
                                                         const RowChunk* __restrict__ tiles, int n_tiles,
@@ -150,65 +152,88 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
                                                         const float* __restrict__ bias, float margin_coef,
                                                         NearEntry* __restrict__ near,
                                                         uint32_t* __restrict__ seg_count, uint32_t seg_cap) {
+    constexpr int TB = kProjTB;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int n_waves = (gridDim.x * blockDim.x) >> 6;
     const int wave = (int)uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     NearEntry* seg = near + (size_t)wave * seg_cap;
     uint32_t cnt = 0;
-    for (int tile = wave; tile < n_tiles; tile += n_waves) {
-        const RowChunk tc = tiles[tile];
-        const bool live = n < tc.nr;
-        const uint8_t* x = imgs[tc.img].desc + (int64_t)(tc.r0 + (live ? n : 0)) * kDim;
-        bf16x8 xb[4];
-        uint32_t sq = 0;
+    for (int t0 = wave * TB; t0 < n_tiles; t0 += n_waves * TB) {
+        RowChunk tc[TB];
+        bool live[TB];
+        bf16x8 xb[TB][4];
+        float base_margin[TB];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const uint2 w = live ? *reinterpret_cast<const uint2*>(x + 32 * ks + 8 * g) : make_uint2(0u, 0u);
-            sq = __builtin_amdgcn_udot4(w.x, w.x, sq, false);
-            sq = __builtin_amdgcn_udot4(w.y, w.y, sq, false);
-            xb[ks] = bytes_to_bf16x8(w);
+        for (int b = 0; b < TB; ++b) {
+            const bool in = t0 + b < n_tiles;
+            tc[b] = tiles[in ? t0 + b : t0];
+            live[b] = in && n < tc[b].nr;
+            const uint8_t* x = imgs[tc[b].img].desc + (int64_t)(tc[b].r0 + (live[b] ? n : 0)) * kDim;
+            uint32_t sq = 0;
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const uint2 w = live[b] ? *reinterpret_cast<const uint2*>(x + 32 * ks + 8 * g) : make_uint2(0u, 0u);
+                sq = __builtin_amdgcn_udot4(w.x, w.x, sq, false);
+                sq = __builtin_amdgcn_udot4(w.y, w.y, sq, false);
+                xb[b][ks] = bytes_to_bf16x8(w);
+            }
+            sq += __shfl_xor(sq, 16);
+            sq += __shfl_xor(sq, 32);
+            base_margin[b] = margin_coef * sqrtf((float)sq) + 0x1p-26f;
         }
-        sq += __shfl_xor(sq, 16);
-        sq += __shfl_xor(sq, 32);
-        const float base_margin = margin_coef * sqrtf((float)sq) + 0x1p-26f;
-        uint64_t w[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+        uint64_t w[TB][3], m[TB][3];
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[b][k] = m[b][k] = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int n_rt = k < 2 ? 4 : kRowTiles - 8;
 #pragma unroll 1
             for (int rw = 0; rw < n_rt; ++rw) {
                 const int rt = 4 * k + rw;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                f32x4 acc[TB];
+#pragma unroll
+                for (int b = 0; b < TB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        load_frag(frag, ((0 * kRowTiles + rt) * 4 + ks) * 64 + lane), xb[ks], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        load_frag(frag, ((1 * kRowTiles + rt) * 4 + ks) * 64 + lane), xb[ks], acc, 0, 0, 0);
-                }
-                const float4 b = reinterpret_cast<const float4*>(bias)[rt * 4 + g];
-                const float bv[4] = {b.x, b.y, b.z, b.w};
+                    const bf16x8 fh = load_frag(frag, ((0 * kRowTiles + rt) * 4 + ks) * 64 + lane);
+                    const bf16x8 fl = load_frag(frag, ((1 * kRowTiles + rt) * 4 + ks) * 64 + lane);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float v = acc[i] - bv[i];
-                    const float M = base_margin + 0x1p-20f * fabsf(bv[i]);
-                    const bool nr = !(fabsf(v) > M);
-                    const bool bit = !nr && v > 0.f;
-                    const int pos = 16 * rw + 4 * g + i;
-                    w[k] |= (uint64_t)bit << pos;
-                    m[k] |= (uint64_t)nr << pos;
+                    for (int b = 0; b < TB; ++b) {
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh, xb[b][ks], acc[b], 0, 0, 0);
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl, xb[b][ks], acc[b], 0, 0, 0);
+                    }
                 }
+                const float4 bq = reinterpret_cast<const float4*>(bias)[rt * 4 + g];
+                const float bv[4] = {bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+                for (int b = 0; b < TB; ++b)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float v = acc[b][i] - bv[i];
+                        const float M = base_margin[b] + 0x1p-20f * fabsf(bv[i]);
+                        const bool nr = !(fabsf(v) > M);
+                        const bool bit = !nr && v > 0.f;
+                        const int pos = 16 * rw + 4 * g + i;
+                        w[b][k] |= (uint64_t)bit << pos;
+                        m[b][k] |= (uint64_t)nr << pos;
+                    }
             }
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            w[k] |= __shfl_xor(w[k], 16);
-            w[k] |= __shfl_xor(w[k], 32);
-            m[k] |= __shfl_xor(m[k], 16);
-            m[k] |= __shfl_xor(m[k], 32);
+        for (int b = 0; b < TB; ++b) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                w[b][k] |= __shfl_xor(w[b][k], 16);
+                w[b][k] |= __shfl_xor(w[b][k], 32);
+                m[b][k] |= __shfl_xor(m[b][k], 16);
+                m[b][k] |= __shfl_xor(m[b][k], 32);
+            }
+            store_code(outs[tc[b].img], tc[b].img, tc[b].r0 + n, g == 0 && live[b], w[b][0], w[b][1], w[b][2],
+                       m[b][0], m[b][1], m[b][2], seg, cnt);
         }
-        store_code(outs[tc.img], tc.img, tc.r0 + n, g == 0 && live, w[0], w[1], w[2], m[0], m[1], m[2], seg, cnt);
     }
     if (lane == 0) seg_count[wave] = cnt;
 }
@@ -326,51 +351,64 @@ __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ i
 }
 
 // ------------------------------------------------------------------ bucket tables
-// One wave per (train image, table): counting sort of the 8-bit keys into 256
-// buckets, stable (ascending index inside a bucket).  Ranks inside a 64-wide
-// chunk come from eight key-bit ballots.
+// One block of kBucketWaves wavefronts per (train image, table): a stable
+// counting sort of the 8-bit keys into 256 buckets (ascending index inside a
+// bucket).  Wave w owns a contiguous slice of the entries: it counts its
+// slice's keys, the block scans the bucket totals and gives each wave its
+// start inside every bucket, then each wave scatters its slice in order.
+// Ranks inside a 64-wide chunk come from eight key-bit ballots.
 template <bool EPI>
-__global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ imgs,
-                                                    const TableOut* __restrict__ touts,
-                                                    const int32_t* __restrict__ train_list) {
-    __shared__ uint32_t cnt[256];
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev* __restrict__ imgs,
+                                                                   const TableOut* __restrict__ touts,
+                                                                   const int32_t* __restrict__ train_list) {
+    __shared__ uint32_t cnt[kBucketWaves][256];  // per-wave counts, then per-wave write positions
+    __shared__ uint32_t wsum[kBucketWaves];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int m = train_list[blockIdx.x / kTables];
     const int t = blockIdx.x % kTables;
     const ImgDev im = imgs[m];
     const TableOut to = touts[m];
     const int n = im.n;
+    // this wave's slice [lo, hi), a whole number of 64-entry chunks
+    const int per = ((n + 64 * kBucketWaves - 1) / (64 * kBucketWaves)) * 64;
+    const int lo = min(n, wv * per), hi = min(n, lo + per);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) cnt[4 * lane + i] = 0;
+    for (int i = 0; i < 4; ++i) cnt[wv][4 * lane + i] = 0;
     __syncthreads();
-    for (int c = 0; c < n; c += 64) {
-        const int j = c + lane;
-        if (j < n) atomicAdd(&cnt[im.keys[6 * (int64_t)j + t]], 1u);
+    for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wv][im.keys[6 * (int64_t)j + t]], 1u);
+    __syncthreads();
+    // thread b of the block owns bucket b (256 threads, 256 buckets)
+    static_assert(64 * kBucketWaves == 256, "one thread per bucket");
+    const int bk = threadIdx.x;
+    uint32_t c[kBucketWaves], tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBucketWaves; ++w) {
+        c[w] = cnt[w][bk];
+        tot += c[w];
     }
-    __syncthreads();
-    uint32_t a[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = cnt[4 * lane + i];
-    const uint32_t tot = a[0] + a[1] + a[2] + a[3];
     const uint32_t incl = wave_incl_scan(tot, lane);
-    uint32_t run = incl - tot;
-    uint32_t* off = to.off + t * kOffStride;
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
+    uint32_t start = incl - tot;
+    for (int w = 0; w < wv; ++w) start += wsum[w];
+    uint32_t* off = to.off + t * kOffStride;
+    off[bk] = start;
+    if (bk == 255) off[256] = start + tot;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        off[4 * lane + i] = run;
-        cnt[4 * lane + i] = run;
-        run += a[i];
+    for (int w = 0; w < kBucketWaves; ++w) {
+        cnt[w][bk] = start;
+        start += c[w];
     }
-    if (lane == 63) off[256] = incl;
     __syncthreads();
     ulonglong2* out_code = reinterpret_cast<ulonglong2*>(to.ent) + (int64_t)t * n;
     uint64_t* out_kid = reinterpret_cast<uint64_t*>(to.ent + (size_t)kTables * n * 16) + (int64_t)t * n;
     float2* out_kp = reinterpret_cast<float2*>(to.ent + (size_t)kTables * n * 24) + (int64_t)t * n;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int c = 0; c < n; c += 64) {
-        const int j = c + lane;
-        const bool valid = j < n;
+    uint32_t* wc = cnt[wv];
+    for (int c0 = lo; c0 < hi; c0 += 64) {
+        const int j = c0 + lane;
+        const bool valid = j < hi;
         const uint32_t key = valid ? im.keys[6 * (int64_t)j + t] : 0u;
         uint64_t eq = __ballot(valid);
 #pragma unroll
@@ -381,16 +419,16 @@ __global__ __launch_bounds__(64) void bucket_kernel(const ImgDev* __restrict__ i
         }
         const uint32_t rank = __popcll(eq & lt_mask);
         uint32_t pos = 0;
-        if (valid) pos = cnt[key] + rank;
-        __syncthreads();
+        if (valid) pos = wc[key] + rank;
+        wave_sync();  // every lane has read its bucket's position before the first lane advances it
         if (valid) {
             const uint16_t* kp = reinterpret_cast<const uint16_t*>(im.keys + 6 * (int64_t)j);
             out_code[pos] = make_ulonglong2(im.codes[2 * (int64_t)j], im.codes[2 * (int64_t)j + 1]);
             out_kid[pos] = (uint64_t)kp[0] | ((uint64_t)kp[1] << 16) | ((uint64_t)kp[2] << 32) | ((uint64_t)j << 48);
             if constexpr (EPI) out_kp[pos] = make_float2(im.kp[2 * (int64_t)j], im.kp[2 * (int64_t)j + 1]);
-            if (rank == 0) cnt[key] = pos + (uint32_t)__popcll(eq);
+            if (rank == 0) wc[key] = pos + (uint32_t)__popcll(eq);
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -459,9 +497,10 @@ hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const Tabl
                          int n_train) {
     if (n_train <= 0) return hipSuccess;
     if (epi)
-        CH_LAUNCH(bucket_kernel<true>, dim3(n_train * kTables), dim3(64), 0, s, imgs, touts, train_list);
+        CH_LAUNCH(bucket_kernel<true>, dim3(n_train * kTables), dim3(64 * kBucketWaves), 0, s, imgs, touts, train_list);
     else
-        CH_LAUNCH(bucket_kernel<false>, dim3(n_train * kTables), dim3(64), 0, s, imgs, touts, train_list);
+        CH_LAUNCH(bucket_kernel<false>, dim3(n_train * kTables), dim3(64 * kBucketWaves), 0, s, imgs, touts,
+                  train_list);
     return hipSuccess;
 }
 
