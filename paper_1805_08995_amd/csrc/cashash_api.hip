@@ -147,6 +147,12 @@ struct cashash_ctx {
     hipEvent_t meta_ev[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     int meta_turn[3] = {0, 0, 0};
     DevBuf near, tables;      // near-margin masks; bucket tables
+    // device-resident row chunks of the last image-size list seen by the
+    // device-memory code builder (column sums: 2048 rows, projection: 16
+    // rows), reused while the sizes repeat
+    std::vector<int32_t> chunk_key;
+    DevBuf chunk_dev;
+    int chunk_ncol = 0, chunk_ntile = 0;
     DevBuf stage, outbuf;     // host-memory mode: resident image slots; per-step outputs
     HostPinned pin[2];        // host-memory mode upload staging
     hipEvent_t pin_ev[2] = {nullptr, nullptr};
@@ -272,7 +278,8 @@ static void destroy_ctx(cashash_ctx* c) {
     }
     for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
                       &c->meta[1][0], &c->meta[1][1], &c->meta[2][0], &c->meta[2][1], &c->near, &c->tables, &c->stage,
-                      &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err})
+                      &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err,
+                      &c->chunk_dev})
         b->release();
     for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
                           &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
@@ -430,28 +437,61 @@ struct CodeJob {
 };
 
 // Column sums over `imgs`, accumulated into c->dS (not cleared here).
-static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
-    std::vector<RowChunk> chunks;
+static void row_chunks(const std::vector<ImgDev>& imgs, int rows, std::vector<RowChunk>& v) {
     for (int m = 0; m < (int)imgs.size(); ++m)
-        for (int r0 = 0; r0 < imgs[m].n; r0 += 2048) chunks.push_back({m, r0, std::min(2048, imgs[m].n - r0), 0});
-    if (chunks.empty()) return CASHASH_OK;
+        for (int r0 = 0; r0 < imgs[m].n; r0 += rows) v.push_back({m, r0, std::min(rows, imgs[m].n - r0), 0});
+}
+
+// The column-sum and projection chunks of imgs on the device, rebuilt (with a
+// synchronous upload) only when the image sizes differ from the last call's.
+static int cached_chunks(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
+    bool same = c->chunk_key.size() == imgs.size();
+    for (size_t m = 0; same && m < imgs.size(); ++m) same = c->chunk_key[m] == imgs[m].n;
+    if (same) return CASHASH_OK;
+    std::vector<RowChunk> v;
+    row_chunks(imgs, 2048, v);
+    const int ncol = (int)v.size();
+    row_chunks(imgs, 16, v);
+    c->chunk_key.clear();
+    RETCHK(c->chunk_dev.ensure(std::max<size_t>(1, v.size()) * sizeof(RowChunk)));
+    HIPCHK(hipStreamSynchronize(c->stream));  // earlier kernels may still read the old chunks
+    if (!v.empty()) HIPCHK(hipMemcpy(c->chunk_dev.p, v.data(), v.size() * sizeof(RowChunk), hipMemcpyHostToDevice));
+    c->chunk_ncol = ncol;
+    c->chunk_ntile = (int)v.size() - ncol;
+    for (const ImgDev& im : imgs) c->chunk_key.push_back(im.n);
+    return CASHASH_OK;
+}
+
+// Column sums of imgs into c->dS; dchunks: device chunks (cached_chunks), or
+// nullptr to build and upload them with the image table.
+static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs, const RowChunk* dchunks = nullptr,
+                      int n_chunks = 0) {
+    std::vector<RowChunk> chunks;
+    if (!dchunks) {
+        row_chunks(imgs, 2048, chunks);
+        n_chunks = (int)chunks.size();
+    }
+    if (n_chunks == 0) return CASHASH_OK;
     Uploader up;
     up.add(imgs);
-    up.add(chunks);
+    if (!dchunks) up.add(chunks);
     std::vector<const void*> d;
     RETCHK(upload_meta(c, up, d, kMetaCodes));
-    HIPCHK(launch_colsum(c->stream, (const ImgDev*)d[0], (const RowChunk*)d[1], (int)chunks.size(),
+    HIPCHK(launch_colsum(c->stream, (const ImgDev*)d[0], dchunks ? dchunks : (const RowChunk*)d[1], n_chunks,
                          c->dS.as<unsigned long long>()));
     return CASHASH_OK;
 }
 
 // Projection + binary64 fix-up of `imgs` into `outs`, given c->dBias and c->dS.
-static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vector<CodeOut> outs, double n_tot) {
+static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vector<CodeOut> outs, double n_tot,
+                       const RowChunk* dtiles = nullptr, int n_tiles = 0) {
     std::vector<RowChunk> tiles;
-    for (int m = 0; m < (int)imgs.size(); ++m)
-        for (int r0 = 0; r0 < imgs[m].n; r0 += 16) tiles.push_back({m, r0, std::min(16, imgs[m].n - r0), 0});
-    if (tiles.empty()) return CASHASH_OK;
-    const int nt = (int)tiles.size();
+    if (!dtiles) {
+        row_chunks(imgs, 16, tiles);
+        n_tiles = (int)tiles.size();
+    }
+    if (n_tiles == 0) return CASHASH_OK;
+    const int nt = n_tiles;
     const bool mfma = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     // near list: one segment per projection wavefront, each large enough for
     // every descriptor that wavefront handles; per-segment counts in front
@@ -467,12 +507,12 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     Uploader up;
     up.add(imgs);
     up.add(outs);
-    up.add(tiles);
+    if (!dtiles) up.add(tiles);
     std::vector<const void*> d;
     RETCHK(upload_meta(c, up, d, kMetaCodes));
     const ImgDev* dI = (const ImgDev*)d[0];
     const CodeOut* dO = (const CodeOut*)d[1];
-    const RowChunk* dT = (const RowChunk*)d[2];
+    const RowChunk* dT = dtiles ? dtiles : (const RowChunk*)d[2];
     const float coef = (float)c->cfg.margin_coef;
     if (mfma) {
         HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
@@ -506,11 +546,13 @@ static int build_codes_device(cashash_ctx* c, const cashash_images* im, uint64_t
         *near_count = 0;
         return CASHASH_OK;
     }
+    RETCHK(cached_chunks(c, imgs));
+    const RowChunk* dch = c->chunk_dev.as<RowChunk>();
     HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
     HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
-    RETCHK(run_colsum(c, imgs));
+    RETCHK(run_colsum(c, imgs, dch, c->chunk_ncol));
     HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot, c->dBias.as<float>()));
-    RETCHK(run_project(c, imgs, outs, n_tot));
+    RETCHK(run_project(c, imgs, outs, n_tot, dch + c->chunk_ncol, c->chunk_ntile));
     unsigned long long cnt = 0;
     HIPCHK(hipMemcpyAsync(&cnt, c->dCount.p, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
