@@ -835,6 +835,19 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         J.imgs[m].off = touts[m].off;
         J.imgs[m].ent = touts[m].ent;
     }
+    // the bucket tables are built while the host plans the pairs
+    MatchPlan P;
+    {
+        Uploader up;
+        up.add(J.imgs);
+        up.add(touts);
+        up.add(train_list);
+        std::vector<const void*> d;
+        RETCHK(upload_meta(c, up, d, kMetaMatch));
+        P.dI = (const ImgDev*)d[0];
+        HIPCHK(launch_bucket(c->stream, J.epi, P.dI, (const TableOut*)d[1], (const int32_t*)d[2],
+                             (int)train_list.size()));
+    }
     std::vector<PairDev> pd(n_pairs);
     for (int64_t p = 0; p < n_pairs; ++p) {
         pd[p].qi = J.pair_q[p];
@@ -844,7 +857,6 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         sum_nt += J.imgs[J.pair_t[p]].n;
         sum_nq += J.imgs[J.pair_q[p]].n;
     }
-    MatchPlan P;
     // batched: items ordered by train image, so the waves running together
     // share one train image's tables in L2
     P.order.resize(n_pairs);
@@ -880,24 +892,17 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     for (size_t i = 0; i < qts.size(); ++i) pts.push_back(pair_tiles(J, P.order, qts[i], &firsts[i]));
 
     Uploader up;
-    up.add(J.imgs);
-    up.add(touts);
-    up.add(train_list);
     up.add(pd);
     for (auto& t : pts) up.add(t);
     std::vector<const void*> d;
     RETCHK(upload_meta(c, up, d, kMetaMatch));
-    P.dI = (const ImgDev*)d[0];
-    const TableOut* dTo = (const TableOut*)d[1];
-    const int32_t* dTrain = (const int32_t*)d[2];
-    P.dP = (const PairDev*)d[3];
+    P.dP = (const PairDev*)d[0];
     P.prm.k = c->cfg.k;
     P.prm.tau = c->cfg.max_hamming;
     P.prm.num2 = (int64_t)c->cfg.ratio_num * c->cfg.ratio_num;
     P.prm.den2 = (int64_t)c->cfg.ratio_den * c->cfg.ratio_den;
     P.prm.max_px = J.max_px;
     unsigned long long* stats = c->dCount.as<unsigned long long>() + 8;
-    HIPCHK(launch_bucket(c->stream, J.epi, P.dI, dTo, dTrain, (int)train_list.size()));
 
     Shape best = cands[0];
     if (tune && cands.size() > 1) {
@@ -910,7 +915,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
             for (const Shape& sh : cands) {
                 const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), sh.qt) - qts.begin());
                 const int64_t n_it = firsts[qi][sample_pairs];
-                RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(),
+                RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(),
                                   firsts[qi][n_pairs]));
                 int64_t dummy_launches = 0;
                 HIPCHK(hipEventRecord(c->ev0, c->stream));
@@ -932,7 +937,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     }
     const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), best.qt) - qts.begin());
     const int64_t n_items = firsts[qi][n_pairs];
-    RETCHK(make_items(c, P, J, best.qt, (const PairTiles*)d[4 + qi], (int32_t)pts[qi].size(), n_items));
+    RETCHK(make_items(c, P, J, best.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(), n_items));
     HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
     RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches, true));
