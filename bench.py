@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "405148e5360302cce43f7782192c658ecaca4ee7eecdf403036e0f5e70b1378f",
+MEASURED_TRAFFIC = {"sources_sha256": "bda4b200e2b8a3db43a0d8806868446674bdbcb702e34240ccbbf187525b6794",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4377288.2 * 1024 * 2), "write_bytes": int(479161.3 * 1024),
+                    "fetch_bytes": int(4491906.2 * 1024 * 2), "write_bytes": int(479183.5 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9756390031}
+                    "valu_insts": 9529668595}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -337,7 +337,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"),
-                     "kernel": "match_kernel<false, 4>", "kernel_ms": round(kernel_ms, 4),
+                     "kernel": "match_kernel<false, 4, false>", "kernel_ms": round(kernel_ms, 4),
                      "valu_issue": measured_valu_issue(
                          f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs", kernel_ms),
                      "note": ("achieved = algorithmic (touched) bytes of the byte model / kernel time; "

@@ -176,8 +176,10 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 // lanes with no candidate; n_union counts candidates that survive the union.
 // CHAIN selects hand-picked instructions for the union test and a chained
 // count (the plain kernels); the band kernels, where few entries get here,
-// keep the compiler's own, which schedules better there.
-template <bool CHAIN>
+// keep the compiler's own, which schedules better there.  FILT = false
+// (tau = 128, no filter): no tau test and no union count here (the caller
+// counts the union from the valid keys).
+template <bool CHAIN, bool FILT>
 __device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint32_t cw, bool live,
                                                const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     // union: drop the candidate if it shares an earlier table's key with the
@@ -201,7 +203,7 @@ __device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint3
         dup = (((y - 0x01010101u) & ~y) | ((y4 - 0x01010101u) & ~y4 & 0xFFu)) & 0x80808080u;
     }
     bool ok = live && !dup;
-    n_union += ok ? 1u : 0u;
+    if constexpr (FILT) n_union += ok ? 1u : 0u;
     uint32_t h;
     if constexpr (CHAIN) {
         h = (uint32_t)__popc((uint32_t)c.x ^ (uint32_t)r.qc0);
@@ -211,36 +213,36 @@ __device__ __forceinline__ uint32_t loaded_key(ulonglong2 c, uint64_t kid, uint3
     } else {
         h = (uint32_t)(__popcll(c.x ^ r.qc0) + __popcll(c.y ^ r.qc1));
     }
-    ok = ok && (int32_t)h <= tau;
+    if constexpr (FILT) ok = ok && (int32_t)h <= tau;
     return ok ? ((h << 16) | (uint32_t)(kid >> 48)) : ~0u;
 }
 
 // The same for the entry at pos, loaded here.
-template <bool CHAIN>
+template <bool CHAIN, bool FILT>
 __device__ __forceinline__ uint32_t entry_key(const TrainView& tv, uint32_t cw, uint32_t pos, bool live,
                                               const QueryRuns& r, int32_t tau, uint32_t& n_union) {
-    return loaded_key<CHAIN>(gload(tv.code + pos), gload(tv.kid + pos), cw, live, r, tau, n_union);
+    return loaded_key<CHAIN, FILT>(gload(tv.code + pos), gload(tv.kid + pos), cw, live, r, tau, n_union);
 }
 
 // Candidate e of the concatenated six bucket runs -> packed key, or ~0u if e
 // is past the runs, outside the epipolar band, a repeat or above tau.
-template <bool EPI, bool ORD>
+template <bool EPI, bool ORD, bool FILT>
 __device__ __forceinline__ uint32_t key_at(uint32_t e, const TrainView& tv, const QueryRuns& r, int32_t tau,
                                            double dd, uint32_t& n_union) {
     uint32_t cw;
     const uint32_t pos = entry_pos<ORD>(e, r, cw);
     bool live = e < r.P6;
     if constexpr (EPI) live = live && in_band(tv, pos, r, dd);
-    return entry_key<!EPI>(tv, cw, pos, live, r, tau, n_union);
+    return entry_key<!EPI, FILT>(tv, cw, pos, live, r, tau, n_union);
 }
 
 // The first C chunks of 64 candidates into register slots, all loads issued
 // together (slots >= C keep ~0u).
-template <bool EPI, int C, int NS>
+template <bool EPI, bool FILT, int C, int NS>
 __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, const TrainView& tv, const QueryRuns& r,
                                               int32_t tau, double dd, uint32_t& n_union) {
 #pragma unroll
-    for (int u = 0; u < C; ++u) kr[u] = key_at<EPI, false>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
+    for (int u = 0; u < C; ++u) kr[u] = key_at<EPI, false, FILT>(64u * u + (uint32_t)lane, tv, r, tau, dd, n_union);
 }
 
 // The same for the plain form when the runs fit 256 candidates: the run
@@ -248,7 +250,7 @@ __device__ __forceinline__ void gather_chunks(uint32_t (&kr)[NS], int lane, cons
 // (o0 = starts at or below 64u, carried from chunk to chunk), and only the
 // last chunk can hold lanes past the runs.  Positions of all C chunks are
 // found first so that their loads are in flight together.
-template <int C, int NS>
+template <bool FILT, int C, int NS>
 __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane, const TrainView& tv,
                                                    const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     uint32_t cw[C], boff[C];  // run word; byte offset of the entry's code (16 bytes per entry)
@@ -272,7 +274,8 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
     }
 #pragma unroll
     for (int u = 0; u < C; ++u)
-        kr[u] = loaded_key<true>(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau, n_union);
+        kr[u] = loaded_key<true, FILT>(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau,
+                                       n_union);
 }
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
@@ -290,10 +293,11 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
 //             ratio test, and the tile's outputs are stored coalesced.
 // Resident blocks per CU each instantiation is compiled for (4 waves per
 // block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
+// FILT = false: the plain kernels' form for tau = 128 (no Hamming filter).
 template <bool EPI, int NS>
 constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 5 : 6) : (EPI ? 4 : 5);
 
-template <bool EPI, int NS>
+template <bool EPI, int NS, bool FILT>
 __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(const ImgDev* __restrict__ imgs,
                                                     const PairDev* __restrict__ pairs,
                                                     const Item* __restrict__ items, int32_t n_items,
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                             const uint32_t i = 64u * u + lane;
                             const bool live = i < n_surv;
                             const uint32_t packed = live ? list[i] : 0u;
-                            kr[u] = entry_key<false>(tv, packed >> 24, live ? (packed & 0xFFFFFFu) : 0u, live, qr, prm.tau,
+                            kr[u] = entry_key<false, true>(tv, packed >> 24, live ? (packed & 0xFFFFFFu) : 0u, live, qr, prm.tau,
                                               st_union);
                         }
                     }
@@ -561,8 +565,8 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     switch (nch) {
 #define GATHER_CASE(C)                                                                            \
     case C:                                                                                       \
-        if constexpr (C <= NS && kMask) gather_chunks_mask<C, NS>(kr, lane, tv, qr, prm.tau, st_union); \
-        else if constexpr (C <= NS) gather_chunks<EPI, C, NS>(kr, lane, tv, qr, prm.tau, dd, st_union); \
+        if constexpr (C <= NS && kMask) gather_chunks_mask<FILT, C, NS>(kr, lane, tv, qr, prm.tau, st_union); \
+        else if constexpr (C <= NS) gather_chunks<EPI, FILT, C, NS>(kr, lane, tv, qr, prm.tau, dd, st_union); \
         break;
                         GATHER_CASE(1)
                         GATHER_CASE(2)
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         uint32_t kv[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            kv[u] = key_at<EPI, kMask>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+                            kv[u] = key_at<EPI, kMask, FILT>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const bool keep = kv[u] != ~0u;
@@ -620,6 +624,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 nc0 = Q.codes[2 * qn];
                 nc1 = Q.codes[2 * qn + 1];
             }
+            if constexpr (!FILT) st_union += lane == 0 ? n_valid : 0u;  // no filter: the union is the valid keys
             const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
             st_ranked += kk;
             if (lane == qi) {
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             for (uint32_t base = 0; base < span; base += 64) {                                        \
                 const uint32_t e = base + lane;                                                       \
                 const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)                          \
-                                             : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);            \
+                                             : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);            \
                 c += (uint32_t)__popcll(__ballot(key >= (lo) && key < (hi)));                         \
             }                                                                                         \
         }                                                                                             \
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         for (uint32_t base = 0; base < span; base += 64) {
                             const uint32_t e = base + lane;
                             const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                         : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);
+                                                         : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);
                             const bool tie = key >= lo && key < hi;
                             const uint64_t mk = __ballot(tie);
                             const uint32_t slot = nt + mbcnt64(mk);
@@ -731,7 +736,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 for (uint32_t base = 0; base < span; base += 64) {
                     const uint32_t e = base + lane;
                     const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                 : key_at<EPI, kMask>(e, tv, qr, prm.tau, dd, dummy);
+                                                 : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);
                     const bool keep = key <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
@@ -823,16 +828,22 @@ hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev*
                         int32_t* o_d1, int32_t* o_d2, unsigned long long* stats) {
     if (n_items <= 0 || grid <= 0) return hipSuccess;
     const dim3 g(grid), b(64 * kWavesPerBlock);
+    const bool filt = prm.tau < kCodeBits;  // a Hamming filter is set
+#define CH_MATCH(E, N, F) \
+    CH_LAUNCH((match_kernel<E, N, F>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats)
     if (epi && ns > 4)
-        CH_LAUNCH((match_kernel<true, 8>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats);
+        CH_MATCH(true, 8, true);
     else if (epi)
-        CH_LAUNCH((match_kernel<true, 4>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats);
+        CH_MATCH(true, 4, true);
+    else if (ns > 4 && filt)
+        CH_MATCH(false, 8, true);
     else if (ns > 4)
-        CH_LAUNCH((match_kernel<false, 8>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2,
-                  stats);
+        CH_MATCH(false, 8, false);
+    else if (filt)
+        CH_MATCH(false, 4, true);
     else
-        CH_LAUNCH((match_kernel<false, 4>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2,
-                  stats);
+        CH_MATCH(false, 4, false);
+#undef CH_MATCH
     return hipSuccess;
 }
 
