@@ -908,11 +908,13 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     if (tune && cands.size() > 1) {
         // time every candidate shape on a prefix of the pairs (outputs are
         // identical for every shape; the full run rewrites them)
-        const int64_t sample_pairs = batched ? std::max<int64_t>(1, std::min<int64_t>(n_pairs, n_pairs / 16 + 8))
+        const int64_t sample_pairs = batched ? std::max<int64_t>(1, std::min<int64_t>(n_pairs, n_pairs / 4 + 8))
                                              : std::min<int64_t>(n_pairs, 12);
-        float best_ms = 1e30f;
-        for (int rep = 0; rep < 2; ++rep)
-            for (const Shape& sh : cands) {
+        // the first round warms up; each shape keeps its fastest later time
+        std::vector<float> shape_ms(cands.size(), 1e30f);
+        for (int rep = 0; rep < 3; ++rep)
+            for (size_t ci = 0; ci < cands.size(); ++ci) {
+                const Shape& sh = cands[ci];
                 const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), sh.qt) - qts.begin());
                 const int64_t n_it = firsts[qi][sample_pairs];
                 RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(),
@@ -925,11 +927,9 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
                 HIPCHK(hipEventSynchronize(c->ev1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-                if (rep == 1 && ms < best_ms) {
-                    best_ms = ms;
-                    best = sh;
-                }
+                if (rep > 0) shape_ms[ci] = std::min(shape_ms[ci], ms);
             }
+        best = cands[(size_t)(std::min_element(shape_ms.begin(), shape_ms.end()) - shape_ms.begin())];
         c->tuned[key] = best;
         tune_cache_store(c, key, best);
     } else if (tune) {
