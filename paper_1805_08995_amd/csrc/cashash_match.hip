@@ -278,25 +278,28 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
                                        n_union);
 }
 
+// Resident blocks per CU each instantiation is compiled for (4 waves per
+// block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
+template <bool EPI, int NS>
+constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 5 : 6) : (EPI ? 4 : 5);
+
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
-//  setup    : lane l loads query l's code, keys and six bucket ranges at once;
-//             each query's values are then broadcast with readlane.
-//  Steps 1-3: per query, the six bucket runs are read four 64-wide chunks at
-//             a time (union by first-table dedupe, Hamming, tau, band); the
-//             index table (histogram over Hamming distance) is built in LDS
-//             and scanned to find the Hamming distance H* of the k-th
-//             candidate; ties at H* are broken by index by counting with
-//             ballots over a binary search of index bits.
+//  setup    : lane l loads query l's keys and six bucket ranges at once and
+//             leaves its run table (and keys) in LDS; the run starts are
+//             broadcast per query with LDS permutes.
+//  Steps 1-3: per query, the six bucket runs are read in 64-wide chunks, all
+//             of a query's chunks in flight together when they fit the
+//             register slots (union by first-table dedupe, Hamming, tau,
+//             band); the index table (histogram over Hamming distance) is
+//             built in LDS and scanned to find the Hamming distance H* of
+//             the k-th candidate; ties at H* are broken by index (up to 64
+//             ranked directly, more by ballot counting over a binary search
+//             of the index bits).
 //  Step 4   : the tile's kept (query, candidate) pairs are measured together,
 //             4 lanes per pair with v_dot4_u32_u8; lane l then takes query l's
 //             distances, picks the nearest and second nearest and applies the
 //             ratio test, and the tile's outputs are stored coalesced.
-// Resident blocks per CU each instantiation is compiled for (4 waves per
-// block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
 // FILT = false: the plain kernels' form for tau = 128 (no Hamming filter).
-template <bool EPI, int NS>
-constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 5 : 6) : (EPI ? 4 : 5);
-
 template <bool EPI, int NS, bool FILT>
 __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(const ImgDev* __restrict__ imgs,
                                                     const PairDev* __restrict__ pairs,

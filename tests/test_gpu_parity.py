@@ -119,6 +119,19 @@ def test_codes_random_matrices_many_sizes(mats):
             _assert_codes(codes, keys, oc, ok, f"seed {seed} {mode}")
 
 
+def test_codes_one_context_changing_sizes(mats):
+    """One context building codes for sets of different image sizes in turn
+    (the device keeps the row chunks of the last sizes; a change must
+    rebuild them), including an empty image and a set seen before."""
+    rng = np.random.default_rng(17)
+    sets = [[synth.desc(rng, n) for n in sizes] for sizes in ((700, 16, 1), (33, 0, 2048, 5), (700, 16, 1))]
+    m = binding.Matcher(*mats)
+    for i, ims in enumerate(sets):
+        oc, ok = oracle.build_codes(ims, *mats)
+        _, codes, keys, _ = _gpu_codes(m, ims)
+        _assert_codes(codes, keys, oc, ok, f"set {i}")
+
+
 # ------------------------------------------------------------------ matching
 
 def _oracle_all(images, oc, ok, pairs, **kw):
