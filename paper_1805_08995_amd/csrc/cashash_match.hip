@@ -155,11 +155,13 @@ __device__ __forceinline__ uint32_t entry_pos(uint32_t e, const QueryRuns& r, ui
 
 // Eq. 1-2: the candidate's keypoint lies within the band around the
 // query's epipolar line.
-__device__ __forceinline__ bool in_band(const TrainView& tv, uint32_t pos, const QueryRuns& r, double dd) {
-    const float2 p = gload(tv.kp + pos);
+__device__ __forceinline__ bool band_ok(float2 p, const QueryRuns& r, double dd) {
     const double xp = (double)p.x, yp = (double)p.y;
     const double ev = (r.la * xp + r.lb * yp) + r.lc;
     return ev * ev <= dd * (r.la * r.la + r.lb * r.lb);
+}
+__device__ __forceinline__ bool in_band(const TrainView& tv, uint32_t pos, const QueryRuns& r, double dd) {
+    return band_ok(gload(tv.kp + pos), r, dd);
 }
 
 // popcount(x) + acc as one v_bcnt_u32_b32 (a dependent chain keeps the
@@ -277,6 +279,9 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
         kr[u] = loaded_key<true, FILT>(c[u], kid[u], cw[u], u + 1 < C || 64u * u + (uint32_t)lane < r.P6, r, tau,
                                        n_union);
 }
+
+// 64-entry chunks of the band-first pass whose keypoint loads are in flight together.
+constexpr int kBandChunks = 2;
 
 // Resident blocks per CU each instantiation is compiled for (4 waves per
 // block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
@@ -520,20 +525,23 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 // the ~1% inside the band are compacted (table, position) into
                 // the LDS list and only they are read in full
                 uint32_t n_surv = 0;
-                for (uint32_t base = 0; base < total; base += 128) {
-                    uint32_t w0, w1;
-                    const uint32_t e0 = base + lane, e1 = base + 64u + lane;
-                    const uint32_t p0 = entry_pos<kMask>(e0, qr, w0), p1 = entry_pos<kMask>(e1, qr, w1);
-                    const bool ok0 = e0 < total && in_band(tv, p0, qr, dd);
-                    const bool ok1 = e1 < total && in_band(tv, p1, qr, dd);
-                    const uint64_t m0 = __ballot(ok0);
-                    const uint32_t s0 = n_surv + mbcnt64(m0);
-                    if (ok0 && s0 < (uint32_t)kListCap) list[s0] = ((w0 & 63u) << 24) | p0;
-                    n_surv += (uint32_t)__popcll(m0);
-                    const uint64_t m1 = __ballot(ok1);
-                    const uint32_t s1 = n_surv + mbcnt64(m1);
-                    if (ok1 && s1 < (uint32_t)kListCap) list[s1] = ((w1 & 63u) << 24) | p1;
-                    n_surv += (uint32_t)__popcll(m1);
+                for (uint32_t base = 0; base < total; base += 64 * kBandChunks) {
+                    // positions are clamped to a valid entry, so the keypoint
+                    // loads of all chunks are issued together, unconditionally
+                    uint32_t w[kBandChunks], ps[kBandChunks];
+                    float2 kp[kBandChunks];
+#pragma unroll
+                    for (int u = 0; u < kBandChunks; ++u) ps[u] = entry_pos<kMask>(base + 64u * u + lane, qr, w[u]);
+#pragma unroll
+                    for (int u = 0; u < kBandChunks; ++u) kp[u] = gload(tv.kp + ps[u]);
+#pragma unroll
+                    for (int u = 0; u < kBandChunks; ++u) {
+                        const bool ok = base + 64u * u + lane < total && band_ok(kp[u], qr, dd);
+                        const uint64_t mk = __ballot(ok);
+                        const uint32_t sl = n_surv + mbcnt64(mk);
+                        if (ok && sl < (uint32_t)kListCap) list[sl] = ((w[u] & 63u) << 24) | ps[u];
+                        n_surv += (uint32_t)__popcll(mk);
+                    }
                 }
                 wave_sync();
                 if (n_surv <= kRegCap && n_surv <= (uint32_t)kListCap) {
