@@ -36,6 +36,7 @@ __device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
 }
 
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t readfirstlane_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     return (uint64_t)readlane((uint32_t)v, l) | ((uint64_t)readlane((uint32_t)(v >> 32), l) << 32);
 }
@@ -280,9 +281,6 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
                                        n_union);
 }
 
-// 64-entry chunks of the band-first pass whose keypoint loads are in flight together.
-constexpr int kBandChunks = 2;
-
 // Resident blocks per CU each instantiation is compiled for (4 waves per
 // block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
 template <bool EPI, int NS>
@@ -524,23 +522,45 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 // band first: only keypoints are read for every bucket entry;
                 // the ~1% inside the band are compacted (table, position) into
                 // the LDS list and only they are read in full
+                // The pass walks the six runs one by one, so a run's table t
+                // is known and its entries are consecutive: first the leading
+                // 64 entries of all six runs with their keypoint loads in
+                // flight together, then the rest of any longer run.  (The
+                // survivors' order differs from the concatenated order; their
+                // keys are ranked by (H, index), which does not depend on it.)
                 uint32_t n_surv = 0;
-                for (uint32_t base = 0; base < total; base += 64 * kBandChunks) {
-                    // positions are clamped to a valid entry, so the keypoint
-                    // loads of all chunks are issued together, unconditionally
-                    uint32_t w[kBandChunks], ps[kBandChunks];
-                    float2 kp[kBandChunks];
+                uint32_t rb[kTables], rl[kTables];  // run start in the table; run length
+                {
+                    const uint32_t st[kTables + 1] = {0u, qr.P1, qr.P2, qr.P3, qr.P4, qr.P5, qr.P6};
 #pragma unroll
-                    for (int u = 0; u < kBandChunks; ++u) ps[u] = entry_pos<kMask>(base + 64u * u + lane, qr, w[u]);
+                    for (int t = 0; t < kTables; ++t) {
+                        rl[t] = st[t + 1] - st[t];
+                        rb[t] = qr.qtab[t] + st[t];
+                    }
+                }
+                auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
+                    const bool ok = i0 + (uint32_t)lane < rl[t] && band_ok(kp, qr, dd);
+                    const uint64_t mk = __ballot(ok);
+                    const uint32_t sl = n_surv + mbcnt64(mk);
+                    if (ok && sl < (uint32_t)kListCap) list[sl] = ((8u * (uint32_t)t) << 24) | pos;
+                    n_surv += (uint32_t)__popcll(mk);
+                };
+                {
+                    uint32_t ps[kTables];
+                    float2 kp[kTables];
 #pragma unroll
-                    for (int u = 0; u < kBandChunks; ++u) kp[u] = gload(tv.kp + ps[u]);
+                    for (int t = 0; t < kTables; ++t) ps[t] = (uint32_t)lane < rl[t] ? rb[t] + (uint32_t)lane : 0u;
 #pragma unroll
-                    for (int u = 0; u < kBandChunks; ++u) {
-                        const bool ok = base + 64u * u + lane < total && band_ok(kp[u], qr, dd);
-                        const uint64_t mk = __ballot(ok);
-                        const uint32_t sl = n_surv + mbcnt64(mk);
-                        if (ok && sl < (uint32_t)kListCap) list[sl] = ((w[u] & 63u) << 24) | ps[u];
-                        n_surv += (uint32_t)__popcll(mk);
+                    for (int t = 0; t < kTables; ++t) kp[t] = gload(tv.kp + ps[t]);
+#pragma unroll
+                    for (int t = 0; t < kTables; ++t) band_chunk(t, 0u, kp[t], ps[t]);
+                }
+#pragma unroll
+                for (int t = 0; t < kTables; ++t) {
+                    const uint32_t len = readfirstlane_u32(rl[t]);
+                    for (uint32_t i0 = 64; i0 < len; i0 += 64) {
+                        const uint32_t pos = i0 + (uint32_t)lane < len ? rb[t] + i0 + (uint32_t)lane : 0u;
+                        band_chunk(t, i0, gload(tv.kp + pos), pos);
                     }
                 }
                 wave_sync();
