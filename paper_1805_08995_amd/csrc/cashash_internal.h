@@ -24,7 +24,7 @@ constexpr int kSelCap = 384;       // per-wave LDS list of a query tile's kept c
 constexpr int kLargeTrain = 9000;
 constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
 constexpr int kMaxTile = 32;       // queries per matcher work item (one per lane of the tile setup)
-constexpr int kBucketWaves = 4;    // wavefronts per (train image, table) counting sort
+constexpr int kBucketWaves = 8;    // wavefronts per (train image, table) counting sort
 constexpr int kProjTB = 4;         // 16-descriptor tiles per projection wavefront group (one fragment load each)
 
 // Per-image view.  desc/codes/keys/kp are the caller's (or staged) buffers;

@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
                                                                    const TableOut* __restrict__ touts,
                                                                    const int32_t* __restrict__ train_list) {
     __shared__ uint32_t cnt[kBucketWaves][256];  // per-wave counts, then per-wave write positions
-    __shared__ uint32_t wsum[kBucketWaves];
+    __shared__ uint32_t wsum[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int m = train_list[blockIdx.x / kTables];
@@ -376,29 +376,34 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
 #pragma unroll
     for (int i = 0; i < 4; ++i) cnt[wv][4 * lane + i] = 0;
     __syncthreads();
+#pragma unroll 4
     for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wv][im.keys[6 * (int64_t)j + t]], 1u);
     __syncthreads();
-    // thread b of the block owns bucket b (256 threads, 256 buckets)
-    static_assert(64 * kBucketWaves == 256, "one thread per bucket");
+    // thread b < 256 of the block owns bucket b
+    static_assert(64 * kBucketWaves >= 256, "a thread per bucket");
     const int bk = threadIdx.x;
-    uint32_t c[kBucketWaves], tot = 0;
+    uint32_t c[kBucketWaves], tot = 0, incl = 0;
+    if (bk < 256) {
 #pragma unroll
-    for (int w = 0; w < kBucketWaves; ++w) {
-        c[w] = cnt[w][bk];
-        tot += c[w];
+        for (int w = 0; w < kBucketWaves; ++w) {
+            c[w] = cnt[w][bk];
+            tot += c[w];
+        }
+        incl = wave_incl_scan(tot, lane);
+        if (lane == 63) wsum[wv] = incl;
     }
-    const uint32_t incl = wave_incl_scan(tot, lane);
-    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    uint32_t start = incl - tot;
-    for (int w = 0; w < wv; ++w) start += wsum[w];
-    uint32_t* off = to.off + t * kOffStride;
-    off[bk] = start;
-    if (bk == 255) off[256] = start + tot;
+    if (bk < 256) {
+        uint32_t start = incl - tot;
+        for (int w = 0; w < wv; ++w) start += wsum[w];
+        uint32_t* off = to.off + t * kOffStride;
+        off[bk] = start;
+        if (bk == 255) off[256] = start + tot;
 #pragma unroll
-    for (int w = 0; w < kBucketWaves; ++w) {
-        cnt[w][bk] = start;
-        start += c[w];
+        for (int w = 0; w < kBucketWaves; ++w) {
+            cnt[w][bk] = start;
+            start += c[w];
+        }
     }
     __syncthreads();
     ulonglong2* out_code = reinterpret_cast<ulonglong2*>(to.ent) + (int64_t)t * n;
