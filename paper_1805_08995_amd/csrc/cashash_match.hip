@@ -35,7 +35,25 @@ __device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t x) {
     return x;
 }
 
+// x as seen through a DPP pattern; lanes with no source receive ~0u.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_hi(uint32_t x) {
+    return __builtin_amdgcn_update_dpp(~0u, x, CTRL, ROW_MASK, 0xf, false);
+}
+
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Minimum over the 64 lanes (the same prefix pattern as wave_scan_dpp; lane
+// 63 ends with the minimum of all).
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+    x = min(x, dpp_hi<0x111, 0xf>(x));
+    x = min(x, dpp_hi<0x112, 0xf>(x));
+    x = min(x, dpp_hi<0x114, 0xf>(x));
+    x = min(x, dpp_hi<0x118, 0xf>(x));
+    x = min(x, dpp_hi<0x142, 0xa>(x));
+    x = min(x, dpp_hi<0x143, 0xc>(x));
+    return readlane(x, 63);
+}
 __device__ __forceinline__ uint32_t readfirstlane_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     return (uint64_t)readlane((uint32_t)v, l) | ((uint64_t)readlane((uint32_t)(v >> 32), l) << 32);
@@ -513,6 +531,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             // full, and the count would take it past 80 VGPRs, the limit for
             // six wavefronts per SIMD)
             constexpr bool kSkipEmpty = NS > 4;
+            // ties needing at most this many picks are ranked by repeated
+            // wave minima (plain kernels, keys in registers)
+            constexpr uint32_t kMinRounds = NS == 4 ? 3u : 2u;
             bool in_regs = true;
             bool gathered = false;
             bool hist_built = true;  // false: the index table still has to be built from kr
@@ -701,6 +722,23 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 const uint32_t need = kk - below;
                 if (ties == need) {
                     tkey = ((hs + 1u) << 16) - 1u;
+                } else if (!EPI && in_regs && need <= kMinRounds) {
+                    // few ties needed: the need-th smallest key at or above
+                    // H* << 16, by rounds of a wave minimum over the keys at
+                    // or above a bound (keys below it, and the ~0u of empty
+                    // slots, wrap to values above every key in range); keys
+                    // are distinct, and the first `ties` keys at or above
+                    // the bound are the ties, so each round finds the next
+                    uint32_t bnd = hs << 16, cur = 0;
+                    for (uint32_t rd = 0; rd < need; ++rd) {
+                        uint32_t m = ~0u;
+#pragma unroll
+                        for (int u = 0; u < NS; ++u)
+                            if (!kSkipEmpty || (uint32_t)u < n_slots) m = min(m, kr[u] - bnd);
+                        cur = bnd + wave_min(m);
+                        bnd = cur + 1u;
+                    }
+                    tkey = cur;
                 } else if (ties <= 64) {
                     // few ties: gather their indices (the index table is no longer
                     // needed) and rank each one against the others
