@@ -25,6 +25,16 @@ __device__ __forceinline__ T gload(const T* p) {
     return *p;  // host pass: parsed only, never run
 #endif
 }
+// Store through a pointer known to address global memory (a generic store
+// would also count against the LDS wait counter).
+template <class T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+#if __HIP_DEVICE_COMPILE__
+    *(__attribute__((address_space(1))) T*)(p) = v;
+#else
+    *p = v;  // host pass: parsed only, never run
+#endif
+}
 typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));

@@ -480,9 +480,11 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
         // plain kernels: the next query's code (a wave-uniform address) is
         // loaded while the current query is ranked
         uint64_t nc0 = 0, nc1 = 0;
+        const ulonglong2* qcodes = reinterpret_cast<const ulonglong2*>(Q.codes);
         if constexpr (!EPI) {
-            nc0 = Q.codes[2 * (int64_t)q0];
-            nc1 = Q.codes[2 * (int64_t)q0 + 1];
+            const ulonglong2 c = gload(qcodes + q0);
+            nc0 = c.x;
+            nc1 = c.y;
         }
         for (int qi = 0; qi < nq; ++qi) {
             QueryRuns qr;
@@ -490,9 +492,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 // the query's code; its keys: from the run table, where the
                 // tile setup left them
                 if constexpr (EPI) {
-                    const int64_t q = (int64_t)q0 + qi;
-                    qr.qc0 = Q.codes[2 * q];
-                    qr.qc1 = Q.codes[2 * q + 1];
+                    const ulonglong2 c = gload(qcodes + ((int64_t)q0 + qi));
+                    qr.qc0 = c.x;
+                    qr.qc1 = c.y;
                 } else {
                     qr.qc0 = nc0;
                     qr.qc1 = nc1;
@@ -502,9 +504,15 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             }
             // run boundaries P1..P5 only meet per-lane compares: broadcast into
             // vector registers (the kernel is short of scalar registers);
-            // P6 bounds the loops and stays scalar
-            qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
-            qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi); qr.P6 = readlane(v_P[5], qi);
+            // P6 bounds the loops and stays scalar.  The 4-slot plain kernel
+            // finds runs by the chunk masks and needs P1..P5 only when the
+            // runs exceed its register slots: it broadcasts them there.
+            auto bounds = [&]() {
+                qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
+                qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi);
+            };
+            if constexpr (!kMask) bounds();
+            qr.P6 = readlane(v_P[5], qi);
             qr.qtab = qtab + kQS * qi;
             if constexpr (EPI) {
                 qr.la = readlane_f64(v_la, qi);
@@ -641,6 +649,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         }
                     }
                 } else {
+                    if constexpr (kMask) bounds();  // the only path that can leave in_regs false
                     for (uint32_t base = 0; base < total; base += 256) {
                         uint32_t kv[4];
 #pragma unroll
@@ -672,9 +681,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             }
             wave_sync();
             if constexpr (!EPI) {
-                const int64_t qn = (int64_t)q0 + min(qi + 1, nq - 1);
-                nc0 = Q.codes[2 * qn];
-                nc1 = Q.codes[2 * qn + 1];
+                const ulonglong2 c = gload(qcodes + ((int64_t)q0 + min(qi + 1, nq - 1)));
+                nc0 = c.x;
+                nc1 = c.y;
             }
             if constexpr (!FILT) st_union += lane == 0 ? n_valid : 0u;  // no filter: the union is the valid keys
             const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
@@ -874,9 +883,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 if (s_rare.den2 * (int64_t)r_d1 < s_rare.num2 * (int64_t)r_d2) r_idx = (int32_t)(uint32_t)best;
             }
             const int64_t o = pr.out + q0 + lane;
-            s_rare.o_idx[o] = r_idx;
-            s_rare.o_d1[o] = r_d1;
-            s_rare.o_d2[o] = r_d2;
+            gstore(s_rare.o_idx + o, r_idx);
+            gstore(s_rare.o_d1 + o, r_d1);
+            gstore(s_rare.o_d2 + o, r_d2);
         }
         wave_sync();
         if (!persistent) break;
