@@ -50,6 +50,17 @@ __device__ __forceinline__ float2 gload(const float2* p) {
     const f32x2_t v = gload(reinterpret_cast<const f32x2_t*>(p));
     return make_float2(v.x, v.y);
 }
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 gload(const uint2* p) {
+    const u32x2_t v = gload(reinterpret_cast<const u32x2_t*>(p));
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(ulonglong2* p, ulonglong2 v) {
+    gstore(reinterpret_cast<u64x2_t*>(p), u64x2_t{v.x, v.y});
+}
+__device__ __forceinline__ void gstore(float2* p, float2 v) {
+    gstore(reinterpret_cast<f32x2_t*>(p), f32x2_t{v.x, v.y});
+}
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();

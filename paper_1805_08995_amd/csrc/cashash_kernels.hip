@@ -118,12 +118,11 @@ __device__ __forceinline__ void store_code(const CodeOut& o, int img, int row, b
                                            uint64_t w2, uint64_t m0, uint64_t m1, uint64_t m2,
                                            NearEntry* __restrict__ seg, uint32_t& cnt) {
     if (live) {
-        o.codes[2 * (int64_t)row] = w0;
-        o.codes[2 * (int64_t)row + 1] = w1;
+        gstore(reinterpret_cast<ulonglong2*>(o.codes) + row, make_ulonglong2(w0, w1));
         uint16_t* kp = reinterpret_cast<uint16_t*>(o.keys + 6 * (int64_t)row);
-        kp[0] = (uint16_t)(w2 & 0xFFFFu);
-        kp[1] = (uint16_t)((w2 >> 16) & 0xFFFFu);
-        kp[2] = (uint16_t)((w2 >> 32) & 0xFFFFu);
+        gstore(kp, (uint16_t)(w2 & 0xFFFFu));
+        gstore(kp + 1, (uint16_t)((w2 >> 16) & 0xFFFFu));
+        gstore(kp + 2, (uint16_t)((w2 >> 32) & 0xFFFFu));
     }
     const bool flagged = live && (m0 | m1 | m2) != 0;
     const uint64_t fm = __ballot(flagged);
@@ -173,7 +172,7 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
             uint32_t sq = 0;
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                const uint2 w = live[b] ? *reinterpret_cast<const uint2*>(x + 32 * ks + 8 * g) : make_uint2(0u, 0u);
+                const uint2 w = live[b] ? gload(reinterpret_cast<const uint2*>(x + 32 * ks + 8 * g)) : make_uint2(0u, 0u);
                 sq = __builtin_amdgcn_udot4(w.x, w.x, sq, false);
                 sq = __builtin_amdgcn_udot4(w.y, w.y, sq, false);
                 xb[b][ks] = bytes_to_bf16x8(w);
@@ -377,7 +376,7 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
     for (int i = 0; i < 4; ++i) cnt[wv][4 * lane + i] = 0;
     __syncthreads();
 #pragma unroll 4
-    for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wv][im.keys[6 * (int64_t)j + t]], 1u);
+    for (int j = lo + lane; j < hi; j += 64) atomicAdd(&cnt[wv][gload(im.keys + 6 * (int64_t)j + t)], 1u);
     __syncthreads();
     // thread b < 256 of the block owns bucket b
     static_assert(64 * kBucketWaves >= 256, "a thread per bucket");
@@ -397,8 +396,8 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
         uint32_t start = incl - tot;
         for (int w = 0; w < wv; ++w) start += wsum[w];
         uint32_t* off = to.off + t * kOffStride;
-        off[bk] = start;
-        if (bk == 255) off[256] = start + tot;
+        gstore(off + bk, start);
+        if (bk == 255) gstore(off + 256, start + tot);
 #pragma unroll
         for (int w = 0; w < kBucketWaves; ++w) {
             cnt[w][bk] = start;
@@ -414,7 +413,7 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
     for (int c0 = lo; c0 < hi; c0 += 64) {
         const int j = c0 + lane;
         const bool valid = j < hi;
-        const uint32_t key = valid ? im.keys[6 * (int64_t)j + t] : 0u;
+        const uint32_t key = valid ? gload(im.keys + 6 * (int64_t)j + t) : 0u;
         uint64_t eq = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -428,9 +427,10 @@ __global__ __launch_bounds__(64 * kBucketWaves) void bucket_kernel(const ImgDev*
         wave_sync();  // every lane has read its bucket's position before the first lane advances it
         if (valid) {
             const uint16_t* kp = reinterpret_cast<const uint16_t*>(im.keys + 6 * (int64_t)j);
-            out_code[pos] = make_ulonglong2(im.codes[2 * (int64_t)j], im.codes[2 * (int64_t)j + 1]);
-            out_kid[pos] = (uint64_t)kp[0] | ((uint64_t)kp[1] << 16) | ((uint64_t)kp[2] << 32) | ((uint64_t)j << 48);
-            if constexpr (EPI) out_kp[pos] = make_float2(im.kp[2 * (int64_t)j], im.kp[2 * (int64_t)j + 1]);
+            gstore(out_code + pos, gload(reinterpret_cast<const ulonglong2*>(im.codes) + j));
+            gstore(out_kid + pos, (uint64_t)gload(kp) | ((uint64_t)gload(kp + 1) << 16) |
+                                      ((uint64_t)gload(kp + 2) << 32) | ((uint64_t)j << 48));
+            if constexpr (EPI) gstore(out_kp + pos, gload(reinterpret_cast<const float2*>(im.kp) + j));
             if (rank == 0) wc[key] = pos + (uint32_t)__popcll(eq);
         }
         wave_sync();

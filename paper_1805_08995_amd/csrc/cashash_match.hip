@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             constexpr bool kSkipEmpty = NS > 4;
             // ties needing at most this many picks are ranked by repeated
             // wave minima (plain kernels, keys in registers)
-            constexpr uint32_t kMinRounds = NS == 4 ? 3u : 2u;
+            constexpr uint32_t kMinRounds = 4u;
             bool in_regs = true;
             bool gathered = false;
             bool hist_built = true;  // false: the index table still has to be built from kr
