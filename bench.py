@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "9ea0ca03504c82f10a01de1a7125c68badd356379ea6e42f203e8cb4d904a429",
+MEASURED_TRAFFIC = {"sources_sha256": "dbeaea41d903ee7b1d61d52cff9d45a6f3fe8e21c45356ffd2cf1b00ec63353c",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4339532.9 * 1024 * 2), "write_bytes": int(479161.2 * 1024),
+                    "fetch_bytes": int(4470784.8 * 1024 * 2), "write_bytes": int(479222.5 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9207988701}
+                    "valu_insts": 9207995608}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

@@ -683,7 +683,7 @@ static void segment_bounds(const MatchJob& J, const std::vector<int64_t>& order,
 }
 
 // Register slots of the matcher instantiation a pair runs in.
-static int slots_for(const MatchJob& J, int64_t p) { return J.imgs[J.pair_t[p]].n > kLargeTrain ? 8 : 4; }
+static int slots_for(const MatchJob& J, int64_t p) { return !J.epi && J.imgs[J.pair_t[p]].n > kLargeTrain ? 8 : 4; }
 
 // Generate the work items of shape qt on the device (into c->items).
 static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int qt, const PairTiles* dPT,

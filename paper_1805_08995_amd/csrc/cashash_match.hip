@@ -300,9 +300,11 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
 }
 
 // Resident blocks per CU each instantiation is compiled for (4 waves per
-// block): the register budget that keeps 6, 5 or 4 wavefronts per SIMD.
+// block): the register budget that keeps 6 or 5 wavefronts per SIMD.  The
+// band kernel spills a few registers at 6, but the extra wavefront hides more
+// of its keypoint-load latency.
 template <bool EPI, int NS>
-constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 5 : 6) : (EPI ? 4 : 5);
+constexpr int kMatchMinBlocks = NS == 4 ? 6 : 5;
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
 //  setup    : lane l loads query l's keys and six bucket ranges at once and
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
     // run words (and, in the 4-slot plain kernel, chunk start masks) per query
     constexpr bool kMask = NS == 4 && !EPI;
-    constexpr int kQS = kMask ? 16 : 8;
+    constexpr int kQS = kMask || EPI ? 16 : 8;
     __shared__ __attribute__((aligned(16))) uint32_t s_qtab[kWavesPerBlock][kMaxTile * kQS];
     // arguments needed only when work is grabbed or a tile is finished, kept
     // in LDS rather than in scalar registers (the kernel is short of them)
@@ -467,12 +469,20 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             }
             wave_sync();
         }
-        double v_la = 0.0, v_lb = 0.0, v_lc = 0.0;
         if constexpr (EPI) {
+            // the query's epipolar line F x, kept in its run table (words
+            // 8-13) rather than in registers for the whole tile
             const double x = (double)gload(Q.kp + 2 * lq), y = (double)gload(Q.kp + 2 * lq + 1);
-            v_la = (pr.F[0] * x + pr.F[1] * y) + pr.F[2];
-            v_lb = (pr.F[3] * x + pr.F[4] * y) + pr.F[5];
-            v_lc = (pr.F[6] * x + pr.F[7] * y) + pr.F[8];
+            const double la = (pr.F[0] * x + pr.F[1] * y) + pr.F[2];
+            const double lb = (pr.F[3] * x + pr.F[4] * y) + pr.F[5];
+            const double lc = (pr.F[6] * x + pr.F[7] * y) + pr.F[8];
+            if (lane < kMaxTile) {
+                double* ql = reinterpret_cast<double*>(qtab + kQS * lane + 8);
+                ql[0] = la;
+                ql[1] = lb;
+                ql[2] = lc;
+            }
+            wave_sync();
         }
         uint32_t my_kk = 0, my_off = 0, sel_n = 0;
         const uint32_t jbits = tv.n > 1 ? 32u - (uint32_t)__clz(tv.n - 1) : 0u;
@@ -515,9 +525,10 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             qr.P6 = readlane(v_P[5], qi);
             qr.qtab = qtab + kQS * qi;
             if constexpr (EPI) {
-                qr.la = readlane_f64(v_la, qi);
-                qr.lb = readlane_f64(v_lb, qi);
-                qr.lc = readlane_f64(v_lc, qi);
+                const double* ql = reinterpret_cast<const double*>(qtab + kQS * qi + 8);
+                qr.la = ql[0];
+                qr.lb = ql[1];
+                qr.lc = ql[2];
             } else {
                 qr.la = qr.lb = qr.lc = 0.0;
             }
@@ -909,10 +920,8 @@ hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev*
     const bool filt = prm.tau < kCodeBits;  // a Hamming filter is set
 #define CH_MATCH(E, N, F) \
     CH_LAUNCH((match_kernel<E, N, F>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats)
-    if (epi && ns > 4)
-        CH_MATCH(true, 8, true);
-    else if (epi)
-        CH_MATCH(true, 4, true);
+    if (epi)
+        CH_MATCH(true, 4, true);  // the band pass keeps only its survivors in the slots
     else if (ns > 4 && filt)
         CH_MATCH(false, 8, true);
     else if (ns > 4)
