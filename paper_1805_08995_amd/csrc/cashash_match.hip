@@ -545,11 +545,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
 #pragma unroll
             for (int u = 0; u < NS; ++u) kr[u] = ~0u;
             uint32_t n_slots = 0;  // register slots that hold candidates (the rest stay ~0u)
-            // the 8-slot kernel skips empty slots in the ranking loops; the
-            // 4-slot kernel keeps no slot count (its slots are nearly always
-            // full, and the count would take it past 80 VGPRs, the limit for
-            // six wavefronts per SIMD)
-            constexpr bool kSkipEmpty = NS > 4;
+            // the 8-slot kernel and the band kernel (whose slots hold only
+            // the band's few survivors) skip empty slots in the ranking and
+            // compaction loops; the 4-slot plain kernel keeps no slot count
+            // (its slots are nearly always full, and the count would take it
+            // past 80 VGPRs, the limit for six wavefronts per SIMD)
+            constexpr bool kSkipEmpty = NS > 4 || EPI;
             // ties needing at most this many picks are ranked by repeated
             // wave minima (plain kernels, keys in registers)
             constexpr uint32_t kMinRounds = 4u;
