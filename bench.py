@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "dbeaea41d903ee7b1d61d52cff9d45a6f3fe8e21c45356ffd2cf1b00ec63353c",
+MEASURED_TRAFFIC = {"sources_sha256": "a7059514f47e0f963d4f3dd403782af79dece911c9e72b3cd944812299d80695",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4470784.8 * 1024 * 2), "write_bytes": int(479222.5 * 1024),
+                    "fetch_bytes": int(4359239.2 * 1024 * 2), "write_bytes": int(479132.1 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9207995608}
+                    "valu_insts": 9144833491}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

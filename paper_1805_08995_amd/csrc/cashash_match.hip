@@ -275,7 +275,7 @@ template <bool FILT, int C, int NS>
 __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane, const TrainView& tv,
                                                    const QueryRuns& r, int32_t tau, uint32_t& n_union) {
     uint32_t cw[C], boff[C];  // run word; byte offset of the entry's code (16 bytes per entry)
-    const uint32_t pre = C > 1 ? r.qtab[6] : 0u;
+    const uint32_t pre = C > 1 ? readfirstlane_u32(r.qtab[6]) : 0u;  // uniform: o0 below is scalar work
 #pragma unroll
     for (int u = 0; u < C; ++u) {
         const uint2 sm = *reinterpret_cast<const uint2*>(r.qtab + 8 + 2 * u);
@@ -334,7 +334,8 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
     __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
-    // run words (and, in the 4-slot plain kernel, chunk start masks) per query
+    // run words per query, plus the chunk start masks (4-slot plain kernel)
+    // or the epipolar line (band kernel)
     constexpr bool kMask = NS == 4 && !EPI;
     constexpr int kQS = kMask || EPI ? 16 : 8;
     __shared__ __attribute__((aligned(16))) uint32_t s_qtab[kWavesPerBlock][kMaxTile * kQS];
