@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "a7059514f47e0f963d4f3dd403782af79dece911c9e72b3cd944812299d80695",
+MEASURED_TRAFFIC = {"sources_sha256": "56d2ec959f583dc41bc2b36d3cb6cc620386a234ff59bda0159ff82747e3df21",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4359239.2 * 1024 * 2), "write_bytes": int(479132.1 * 1024),
+                    "fetch_bytes": int(4609371.2 * 1024 * 2), "write_bytes": int(479193.5 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9144833491}
+                    "valu_insts": 9144852413}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
                 qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi);
             };
-            if constexpr (!kMask) bounds();
+            if constexpr (!kMask && !EPI) bounds();
             qr.P6 = readlane(v_P[5], qi);
             qr.qtab = qtab + kQS * qi;
             if constexpr (EPI) {
@@ -573,11 +573,15 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 uint32_t n_surv = 0;
                 uint32_t rb[kTables], rl[kTables];  // run start in the table; run length
                 {
-                    const uint32_t st[kTables + 1] = {0u, qr.P1, qr.P2, qr.P3, qr.P4, qr.P5, qr.P6};
+                    // uniform per query: scalar registers (readlane of the
+                    // per-lane starts, the run table read once)
+                    const uint32_t st[kTables + 1] = {0u, readlane(v_P[0], qi), readlane(v_P[1], qi),
+                                                      readlane(v_P[2], qi), readlane(v_P[3], qi),
+                                                      readlane(v_P[4], qi), qr.P6};
 #pragma unroll
                     for (int t = 0; t < kTables; ++t) {
                         rl[t] = st[t + 1] - st[t];
-                        rb[t] = qr.qtab[t] + st[t];
+                        rb[t] = readfirstlane_u32(qr.qtab[t]) + st[t];
                     }
                 }
                 auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
@@ -629,6 +633,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             if (gathered) {
                 hist_built = false;
             } else {
+                if constexpr (EPI) bounds();  // the band kernel's only path that reads them
                 clear_hist(hist, lane);
                 if (total <= kRegCap) {
                     // common case: every bucket entry of the query fits the
