@@ -306,6 +306,30 @@ def test_epipolar_small_set(mats):
     _assert_match(got, plain, "epipolar huge band")
 
 
+@pytest.mark.parametrize("k", [1, 10])
+def test_epipolar_unbounded_candidates_huge_band(mats, k):
+    """Zero bucket rows and a band wider than the images: every bucket entry
+    (6 x 1080 per query) survives the band pass, more than the register
+    slots and the LDS list hold, so the band kernel takes its fallback path
+    (band test per entry during the gather); results equal plain matching."""
+    _say(f"epipolar unbounded candidates k={k}")
+    rc, _ = mats
+    rb = np.zeros((6, 8, 128))
+    rng = np.random.default_rng(14)
+    A = synth.desc(rng, 200)
+    B = np.concatenate([synth.noisy(rng, A[:80]), synth.desc(rng, 1000)])
+    oc, ok = oracle.build_codes([A, B], rc, rb)
+    pairs = np.array([[0, 1], [1, 0]], np.int32)
+    exp = _oracle_all([A, B], oc, ok, pairs, k=k)
+    m = binding.Matcher(rc, rb, k=k)
+    dimgs, codes, keys, _ = _gpu_codes(m, [A, B])
+    kp = [rng.uniform(0, 1000, (len(A), 2)).astype(np.float32), rng.uniform(0, 1000, (len(B), 2)).astype(np.float32)]
+    F = np.tile(np.array([[0, 0, 0, 0, 0, -1, 0, 1, 0]], np.float64), (2, 1))
+    got, st = m.match_pairs_epipolar(dimgs, codes, keys, _dev(kp), pairs, F, 1e7)
+    _assert_match(got, exp, f"epipolar unbounded k={k}")
+    assert st["union_size"] == 200 * 1080 + 1080 * 200
+
+
 def test_epipolar_rectified_boundary(mats):
     """Rectified F: keep iff (y - y')^2 <= d^2; y' = 4 kept, 4 + 2^-21 dropped."""
     F = np.array([[0, 0, 0, 0, 0, -1, 0, 1, 0]], np.float64)
