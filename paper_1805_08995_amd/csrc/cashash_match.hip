@@ -587,9 +587,11 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
                     const bool ok = i0 + (uint32_t)lane < rl[t] && band_ok(kp, qr, dd);
                     const uint64_t mk = __ballot(ok);
-                    const uint32_t sl = n_surv + mbcnt64(mk);
-                    if (ok && sl < (uint32_t)kListCap) list[sl] = ((8u * (uint32_t)t) << 24) | pos;
-                    n_surv += (uint32_t)__popcll(mk);
+                    if (mk != 0) {  // wave-uniform; most chunks have no survivor
+                        const uint32_t sl = n_surv + mbcnt64(mk);
+                        if (ok && sl < (uint32_t)kListCap) list[sl] = ((8u * (uint32_t)t) << 24) | pos;
+                        n_surv += (uint32_t)__popcll(mk);
+                    }
                 };
                 {
                     uint32_t ps[kTables];
