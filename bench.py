@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
 # sources they were taken on (sha256 over MATCHER_SOURCES, in order).
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "a7e96e78824d0d3171e05c2538d008513b88ab514c73a1d1c25cf6b455e637c0",
+MEASURED_TRAFFIC = {"sources_sha256": "7a66e258b8c437551b41b488a3763f60b0dbb83105040317a1412adab5bfcb8a",
                     "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4428824.9 * 1024 * 2), "write_bytes": int(479173.2 * 1024),
+                    "fetch_bytes": int(4298799.8 * 1024 * 2), "write_bytes": int(479093.1 * 1024),
                     # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9144844848}
+                    "valu_insts": 9139892569}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles, 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

@@ -683,7 +683,10 @@ static void segment_bounds(const MatchJob& J, const std::vector<int64_t>& order,
 }
 
 // Register slots of the matcher instantiation a pair runs in.
-static int slots_for(const MatchJob& J, int64_t p) { return !J.epi && J.imgs[J.pair_t[p]].n > kLargeTrain ? 8 : 4; }
+static int slots_for(const MatchJob& J, int64_t p) {
+    const int n = J.imgs[J.pair_t[p]].n;
+    return J.epi || n <= kLargeTrain ? 4 : n <= kHugeTrain ? 6 : 8;
+}
 
 // Generate the work items of shape qt on the device (into c->items).
 static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int qt, const PairTiles* dPT,
@@ -863,8 +866,8 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     if (batched) {
         // stable counting sort by (register-slot group, train image)
-        std::vector<int64_t> start((size_t)2 * n_img + 1, 0);
-        auto bucket = [&](int64_t p) { return (slots_for(J, p) == 8 ? n_img : 0) + J.pair_t[p]; };
+        std::vector<int64_t> start((size_t)3 * n_img + 1, 0);
+        auto bucket = [&](int64_t p) { return (slots_for(J, p) / 2 - 2) * n_img + J.pair_t[p]; };
         for (int64_t p = 0; p < n_pairs; ++p) start[(size_t)bucket(p) + 1]++;
         for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
         for (int64_t p = 0; p < n_pairs; ++p) P.order[(size_t)start[(size_t)bucket(p)]++] = p;

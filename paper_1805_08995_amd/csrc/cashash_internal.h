@@ -16,13 +16,14 @@ constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
 constexpr int kMaxK = 64;
 constexpr int kListCap = 512;      // per-wave LDS candidate list (u32 keys); reused for tile distances
 constexpr int kSelCap = 384;       // per-wave LDS list of a query tile's kept candidates
-// A query's candidate keys are held in NS 64-wide register slots (NS = 4 or
-// 8, a template parameter of the matcher); queries with more candidates use
-// the LDS list.  Plain-form pairs whose train image has more than
-// kLargeTrain points run in the 8-slot instantiation, the rest in the 4-slot
-// one (fewer registers, more resident waves).  The band (epipolar) form
-// always runs 4 slots: only the survivors of its band pass fill them.
+// A query's candidate keys are held in NS 64-wide register slots (NS = 4, 6
+// or 8, a template parameter of the matcher); queries with more candidates
+// use the LDS list.  Plain-form pairs run 4 slots up to kLargeTrain train
+// points, 6 up to kHugeTrain and 8 above (fewer slots: fewer registers, more
+// resident waves).  The band (epipolar) form always runs 4 slots: only the
+// survivors of its band pass fill them.
 constexpr int kLargeTrain = 9000;
+constexpr int kHugeTrain = 14000;  // plain form: above it, 8 slots; above kLargeTrain, 6
 constexpr int kWavesPerBlock = 4;  // matcher block = 4 waves
 constexpr int kMaxTile = 32;       // queries per matcher work item (one per lane of the tile setup)
 constexpr int kBucketWaves = 8;    // wavefronts per (train image, table) counting sort

@@ -126,7 +126,7 @@ __device__ __forceinline__ void clear_hist(uint32_t* hist, int lane) {
 //  by table (most kernels): P1..P5 are the run starts of tables 1..5 and P6
 //    the number of bucket entries; the number of starts at or below e is its
 //    table t, and qtab[t] = C.
-//  by ordinal (the 4-slot plain kernel): P1..P5 are the starts of the
+//  by ordinal (the 4- and 6-slot plain kernels): P1..P5 are the starts of the
 //    non-empty runs after the first non-empty one (~0u for the other runs),
 //    whose count at or below e is the ordinal o of e's run among the
 //    non-empty runs, and qtab[o] = (16 C << 6) | 8t.  qtab[8 + 2u .. 9 + 2u]
@@ -334,10 +334,11 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
     __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
     __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
-    // run words per query, plus the chunk start masks (4-slot plain kernel)
+    // run words per query, plus the chunk start masks (4- and 6-slot plain
+    // kernels)
     // or the epipolar line (band kernel)
-    constexpr bool kMask = NS == 4 && !EPI;
-    constexpr int kQS = kMask || EPI ? 16 : 8;
+    constexpr bool kMask = (NS == 4 || NS == 6) && !EPI;
+    constexpr int kQS = kMask ? 8 + 2 * NS : (EPI ? 16 : 8);
     __shared__ __attribute__((aligned(16))) uint32_t s_qtab[kWavesPerBlock][kMaxTile * kQS];
     // arguments needed only when work is grabbed or a tile is finished, kept
     // in LDS rather than in scalar registers (the kernel is short of them)
@@ -428,12 +429,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             const bool own = lane < kMaxTile;
             if constexpr (kMask) {
                 if (own) {
-                    reinterpret_cast<uint4*>(qt + 8)[0] = make_uint4(0u, 0u, 0u, 0u);
-                    reinterpret_cast<uint4*>(qt + 8)[1] = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                    for (int i = 0; i < NS / 2; ++i) reinterpret_cast<uint4*>(qt + 8)[i] = make_uint4(0u, 0u, 0u, 0u);
                 }
             }
             uint32_t acc = 0, cnt = 0, cu[kTables];  // entries and non-empty runs before table t
-            uint32_t pre = 0;                         // run starts at or below 64, 128, 192 (3 bits each)
+            uint32_t pre = 0;                         // run starts at or below 64, 128, ... (3 bits each)
 #pragma unroll
             for (int t = 0; t < kTables; ++t) {
                 const uint32_t v = (uint32_t)((v_qk >> (8 * t)) & 0xFFu);
@@ -445,11 +446,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     if (t > 0) v_P[t - 1] = (len != 0 && cnt != 0) ? start : ~0u;
                     if (len != 0) {
                         if (own) qt[cnt] = (cu[t] << 10) | (8u * (uint32_t)t);
-                        if (own && cnt != 0 && start <= 256u)
+                        if (own && cnt != 0 && start <= 64u * NS)
                             atomicOr(qt + 8 + ((start - 1u) >> 5), 1u << ((start - 1u) & 31u));
-                        if (cnt != 0)
-                            pre += (uint32_t)(start <= 64u) + ((uint32_t)(start <= 128u) << 3) +
-                                   ((uint32_t)(start <= 192u) << 6);
+                        if (cnt != 0) {
+#pragma unroll
+                            for (int bnd = 1; bnd < NS; ++bnd) pre += (uint32_t)(start <= 64u * bnd) << (3 * (bnd - 1));
+                        }
                         ++cnt;
                     }
                 } else if (t > 0) {
@@ -515,9 +517,9 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             }
             // run boundaries P1..P5 only meet per-lane compares: broadcast into
             // vector registers (the kernel is short of scalar registers);
-            // P6 bounds the loops and stays scalar.  The 4-slot plain kernel
-            // finds runs by the chunk masks and needs P1..P5 only when the
-            // runs exceed its register slots: it broadcasts them there.
+            // P6 bounds the loops and stays scalar.  The masked plain kernels
+            // find runs by the chunk masks and need P1..P5 only when the runs
+            // exceed their register slots: they broadcast them there.
             auto bounds = [&]() {
                 qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
                 qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi);
@@ -931,10 +933,14 @@ hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev*
     CH_LAUNCH((match_kernel<E, N, F>), g, b, 0, s, imgs, pairs, items, n_items, counter, prm, o_idx, o_d1, o_d2, stats)
     if (epi)
         CH_MATCH(true, 4, true);  // the band pass keeps only its survivors in the slots
-    else if (ns > 4 && filt)
+    else if (ns > 6 && filt)
         CH_MATCH(false, 8, true);
-    else if (ns > 4)
+    else if (ns > 6)
         CH_MATCH(false, 8, false);
+    else if (ns > 4 && filt)
+        CH_MATCH(false, 6, true);
+    else if (ns > 4)
+        CH_MATCH(false, 6, false);
     else if (filt)
         CH_MATCH(false, 4, true);
     else
