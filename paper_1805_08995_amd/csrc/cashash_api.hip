@@ -60,13 +60,17 @@ static int fail(int code, const char* fmt, ...) {
     } while (0)
 
 // ------------------------------------------------------------------ buffers
+// Waits for the work queued on the context's own streams (defined below).
+static void quiesce(const cashash_ctx* c);
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    const cashash_ctx* owner = nullptr;  // whose streams may still use the block
     int ensure(size_t n) {
         if (n <= cap && p) return CASHASH_OK;
         if (p) {
-            hipDeviceSynchronize();  // kernels in flight may still read the old block
+            quiesce(owner);  // the context's kernels in flight may still read the old block
             hipFree(p);
         }
         p = nullptr;
@@ -184,7 +188,22 @@ struct cashash_ctx {
     DevBuf geo_sub, geo_m1, geo_pair, geo_err;
     hipEvent_t geo_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double geo_ms[4] = {0, 0, 0, 0};
+    // recorded on the caller's legacy default stream at each entry point when
+    // the context runs on a stream of its own (cfg.stream == NULL)
+    hipEvent_t caller_ev = nullptr;
 };
+
+static void quiesce(const cashash_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->copy_stream) hipStreamSynchronize(c->copy_stream);
+}
+
+static std::vector<DevBuf*> dev_bufs(cashash_ctx* c) {
+    return {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
+            &c->meta[1][0], &c->meta[1][1], &c->meta[2][0], &c->meta[2][1], &c->near, &c->tables, &c->stage,
+            &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err, &c->chunk_dev};
+}
 
 static int validate_config(const cashash_config* c) {
     if (c->k < 1 || c->k > CASHASH_MAX_K) return fail(CASHASH_E_LIMIT, "k=%d outside 1..%d", c->k, CASHASH_MAX_K);
@@ -276,11 +295,7 @@ static void destroy_ctx(cashash_ctx* c) {
         hipStreamSynchronize(c->copy_stream);
         hipStreamDestroy(c->copy_stream);
     }
-    for (DevBuf* b : {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
-                      &c->meta[1][0], &c->meta[1][1], &c->meta[2][0], &c->meta[2][1], &c->near, &c->tables, &c->stage,
-                      &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err,
-                      &c->chunk_dev})
-        b->release();
+    for (DevBuf* b : dev_bufs(c)) b->release();
     for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
                           &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
         h->release();
@@ -288,7 +303,7 @@ static void destroy_ctx(cashash_ctx* c) {
                          c->meta_ev[2][0], c->meta_ev[2][1], c->geo_ev[0], c->geo_ev[1], c->geo_ev[2], c->geo_ev[3],
                          c->geo_ev[4], c->pin_ev[0], c->pin_ev[1],
                          c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
-                         c->slot_free_ev[1], c->slot_free_ev[2]})
+                         c->slot_free_ev[1], c->slot_free_ev[2], c->caller_ev})
         if (e) hipEventDestroy(e);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -338,6 +353,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     RETCHK(check_rows(R, n.margin_coef));
     cashash_ctx* c = new cashash_ctx();
     c->R64 = std::move(R);
+    for (DevBuf* b : dev_bufs(c)) b->owner = c;
     auto bail = [&](int code) {
         std::string keep = g_err;
         destroy_ctx(c);
@@ -363,7 +379,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1],
                           &c->meta_ev[2][0], &c->meta_ev[2][1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
                           &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
-                          &c->slot_free_ev[2]})
+                          &c->slot_free_ev[2], &c->caller_ev})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
     if ((r = c->pin_small.ensure(4096))) return bail(r);
@@ -392,6 +408,19 @@ extern "C" int cashash_last_kernel_ms(cashash_ctx* c, double* ms, int64_t* launc
 // ------------------------------------------------------------------ helpers
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// A caller that passes no stream works on the legacy default stream, where
+// it may still have work queued that writes this call's inputs or reads its
+// output buffers (a caching allocator hands out blocks as soon as their last
+// use is queued).  The context's own stream is non-blocking, so it is made
+// to wait for everything queued there so far.  A caller stream given in
+// cfg.stream is the context's stream itself and is ordered already.
+static int follow_caller(cashash_ctx* c) {
+    if (!c->own_stream) return CASHASH_OK;
+    HIPCHK(hipEventRecord(c->caller_ev, nullptr));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->caller_ev, 0));
+    return CASHASH_OK;
 }
 
 // Uploads small tables on the compute stream (so they follow the kernels that
@@ -1362,6 +1391,7 @@ extern "C" int cashash_build_codes(cashash_ctx* c, const cashash_images* im, uin
     RETCHK(check_images(im));
     if (im->n_images > 0 && (!codes_out || !keys_out)) return fail(CASHASH_E_INVAL, "null output arrays");
     zero_stats(stats);
+    RETCHK(follow_caller(c));
     const double t0 = now_ms();
     int64_t near_count = 0;
     if (c->cfg.mem == CASHASH_MEM_DEVICE) {
@@ -1394,6 +1424,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
         for (int64_t i = 0; i < 9 * n_pairs; ++i)
             if (!std::isfinite(F[i])) return fail(CASHASH_E_INVAL, "F of pair %lld is not finite", (long long)(i / 9));
     }
+    RETCHK(follow_caller(c));
     const double t0 = now_ms();
     MatchJob J;
     J.epi = epi;
@@ -1532,6 +1563,7 @@ extern "C" int cashash_select_top_scale(cashash_ctx* c, int32_t n_images, const 
     RETCHK(check_counts(n_images, n_feat));
     if (cashash_subset_size(0, frac_num, frac_den) < 0) return fail(CASHASH_E_INVAL, "need 0 < frac_num <= frac_den");
     if (n_images > 0 && (!scales || !rows_out)) return fail(CASHASH_E_INVAL, "null scale or row arrays");
+    RETCHK(follow_caller(c));
     RETCHK(run_select(c, n_images, scales, n_feat, frac_num, frac_den, rows_out));
     HIPCHK(hipStreamSynchronize(c->stream));
     return CASHASH_OK;
@@ -1598,6 +1630,7 @@ extern "C" int cashash_gather_rows(cashash_ctx* c, int32_t n_images, const int32
             misaligned(x.o_kp, 4))
             return fail(CASHASH_E_INVAL, "image %d: misaligned buffer", m);
     }
+    RETCHK(follow_caller(c));
     RETCHK(clear_geo_err(c));
     RETCHK(run_gather(c, g));
     return read_geo_err(c);
@@ -1705,6 +1738,7 @@ extern "C" int cashash_estimate_fundamental(cashash_ctx* c, int32_t n_images, co
     }
     if (total > 0 && (!match_idx || misaligned(match_idx, 4)))
         return fail(CASHASH_E_INVAL, "null or misaligned match_idx");
+    RETCHK(follow_caller(c));
     RETCHK(clear_geo_err(c));
     RETCHK(run_fundamental(c, n_images, n_feat, kp_xy, n_pairs, pairs, out, match_idx, rand8, n_hyp, thr_px,
                            min_matches));
@@ -1731,6 +1765,7 @@ extern "C" int cashash_match_pairs_geometric(cashash_ctx* c, const cashash_image
     if (n_pairs == 0) return CASHASH_OK;
     if (!codes || !keys || !kp_xy || !scales || !F_out || !n_matches || !n_inliers || !status)
         return fail(CASHASH_E_INVAL, "null argument");
+    RETCHK(follow_caller(c));
     const double t0 = now_ms();
     const int n_img = im->n_images;
     std::vector<char> used(n_img, 0);
@@ -2150,6 +2185,20 @@ extern "C" int cashash_match_pairs_disk(cashash_ctx* c, const char* set_path, co
     hash = fnv1a(hash, pairs, (size_t)n_pairs * 8);
     hash = fnv1a(hash, &slot, 8);
     hash = fnv1a(hash, &n_steps, 8);
+    // the matching configuration (it decides every output) ...
+    {
+        const int32_t cfgv[5] = {c->cfg.k, c->cfg.ratio_num, c->cfg.ratio_den, c->cfg.max_hamming, c->cfg.mode};
+        hash = fnv1a(hash, cfgv, sizeof cfgv);
+    }
+    // ... and the identity of the set and codes files: size and modification
+    // time, so that a regenerated file invalidates the progress
+    for (int fd : {S.f.fd, cf.fd}) {
+        struct stat st;
+        if (::fstat(fd, &st) != 0) return fail(CASHASH_E_IO, "cannot stat an input file");
+        const int64_t id[4] = {(int64_t)st.st_size, (int64_t)st.st_mtim.tv_sec, (int64_t)st.st_mtim.tv_nsec,
+                               (int64_t)st.st_ino};
+        hash = fnv1a(hash, id, sizeof id);
+    }
     std::vector<uint8_t> done((size_t)n_steps, 0);
     Fd pf;
     if (progress_path) {

@@ -16,6 +16,8 @@ projections of 3-D points by pinhole cameras.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -143,10 +145,11 @@ def uneven_set(seed: int = 4, n_images: int = 2000, lo: int = 1000, hi: int = 20
     img_ss = g_imgs.spawn(n_images)
     images: list = [None] * n_images
     truth: list = [None] * n_images
-    for s in range(n_scenes):
+
+    def scene(s):
         members_of = range(s, n_images, n_scenes)
         if not len(members_of):
-            continue
+            return
         pool = desc(np.random.default_rng(pool_ss[s]), hi)
         for i in members_of:
             r = np.random.default_rng(img_ss[i])
@@ -158,6 +161,10 @@ def uneven_set(seed: int = 4, n_images: int = 2000, lo: int = 1000, hi: int = 20
             perm = r.permutation(n)
             images[i] = np.ascontiguousarray(x[perm])
             truth[i] = t[perm]
+
+    # scenes are independent (own generators), so threads do not change the bytes
+    with ThreadPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(scene, range(n_scenes)))
     rp = np.random.default_rng(g_pairs)
     pairs = []
     for i in range(n_images):

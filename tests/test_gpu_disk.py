@@ -1,9 +1,11 @@
 """Disk level of the data scheduling on the GPU: codes and matches streamed
-from a set file in groups equal the in-memory results bit for bit, and an
-interrupted matching run resumes from its progress file."""
+from a set file in groups equal the oracle's bit for bit, an interrupted
+matching run resumes from its progress file, and a change of matching
+configuration or of the codes file invalidates that progress."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1805_08995_amd import binding, synth
 
 pytestmark = pytest.mark.gpu
@@ -27,16 +29,14 @@ def workload(tmp_path_factory):
     set_path = d / "set.chs"
     binding.set_write(set_path, imgs)
     mats = synth.projection_matrices()
-    md = binding.Matcher(*mats, mem="device")
-    dev = [torch.from_numpy(im).cuda() for im in imgs]
-    codes, keys, _ = md.build_codes(dev)
-    ref_codes = np.concatenate([c.cpu().numpy().view(np.uint64) for c in codes])
-    ref_keys = np.concatenate([k.cpu().numpy() for k in keys])
-    out, _ = md.match_pairs(dev, codes, keys, pairs)
-    ref = [o.cpu().numpy() for o in out]
-    md.close()
+    # expected values: the CPU oracle
+    oc, ok = oracle.build_codes(imgs, *mats)
+    ref_codes = np.concatenate(oc)
+    ref_keys = np.concatenate(ok)
+    ref = list(oracle.match_pairs(imgs, oc, ok, pairs, k=10))
+    ref_tau = list(oracle.match_pairs(imgs, oc, ok, pairs, k=10, tau=44))
     return dict(imgs=imgs, pairs=pairs, dir=d, set=set_path, mats=mats, ref_codes=ref_codes, ref_keys=ref_keys,
-                ref=ref)
+                ref=ref, ref_tau=ref_tau)
 
 
 def _host_matcher(w, device_budget=6 << 20):
@@ -115,3 +115,31 @@ def test_disk_errors(workload, tmp_path):
     with pytest.raises(binding.CashashError) as e:
         m.build_codes_disk(w["set"], tmp_path / "c2.chc", 1000)   # an image alone exceeds a group
     assert e.value.code == binding.E_NOMEM
+
+
+def test_resume_progress_tied_to_config_and_codes(workload):
+    """Progress of a finished run is not reused by a run with another Hamming
+    threshold (every pair is matched again, and the outputs are the oracle's
+    for that threshold), nor after the codes file is written again."""
+    w = workload
+    m = _host_matcher(w)
+    codes_path = w["dir"] / "codes5.chc"
+    m.build_codes_disk(w["set"], codes_path, host_budget_bytes=1 << 30)
+    out_path, prog = w["dir"] / "out5.cho", w["dir"] / "out5.prog"
+    budget = 3 * 700_000
+    left, st = m.match_pairs_disk(w["set"], codes_path, w["pairs"], out_path, budget, prog)
+    assert left == 0 and st["pairs"] == len(w["pairs"])
+    mt = binding.Matcher(*w["mats"], mem="host", device_budget_bytes=6 << 20, max_hamming=44)
+    left, st = mt.match_pairs_disk(w["set"], codes_path, w["pairs"], out_path, budget, prog)
+    assert left == 0 and st["pairs"] == len(w["pairs"])
+    for g, r in zip(binding.read_output_file(out_path), w["ref_tau"]):
+        assert np.array_equal(g, r)
+    # same config as the last run: nothing to do
+    left, st = mt.match_pairs_disk(w["set"], codes_path, w["pairs"], out_path, budget, prog)
+    assert left == 0 and st["pairs"] == 0
+    # the codes file written again: progress is stale
+    mt.build_codes_disk(w["set"], codes_path, host_budget_bytes=1 << 30)
+    left, st = mt.match_pairs_disk(w["set"], codes_path, w["pairs"], out_path, budget, prog)
+    assert left == 0 and st["pairs"] == len(w["pairs"])
+    for g, r in zip(binding.read_output_file(out_path), w["ref_tau"]):
+        assert np.array_equal(g, r)

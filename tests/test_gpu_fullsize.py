@@ -1,27 +1,43 @@
-"""Full-size workloads on the GPU, checked against the oracle on sampled
-outputs (the oracle cannot match every pair in test time) and, where two GPU
-forms exist, against each other in full.
+"""Full-size workloads on the GPU, every pair checked against the oracle.
+
+The oracle's outputs of these workloads are stored as digests (per image:
+codes and keys; per pair: match_idx, d1sq and d2sq over all its queries) in
+tests/golden/fullsize_<name>.npz, written by tests/golden/make_fullsize_digests.py
+from the CPU oracle alone.  The GPU's outputs are digested the same way and
+every image and every pair must agree.
 
   scenes   : 100 images x 8000 features, 4950 exhaustive pairs, in the launch
-             configuration bench.py times (device memory, batched, autotuned);
-             codes and keys compared in full.
+             configuration bench.py times (device memory, batched, autotuned),
+             and in the plain per-pair form.
   uneven   : 2000 images of 1000-20000 features (log-uniform), 30 partners
-             each (60000 pairs); device mode, and host mode streamed in
-             scheduled blocks under a 3 GB device budget.
+             each (60000 pairs; the 4-, 6- and 8-slot matchers); device mode,
+             and host mode streamed in scheduled blocks under a 3 GB device
+             budget.
   epipolar : 500 images x 12000 features, 15000 neighbour pairs, 4 px band.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_1805_08995_amd import binding, synth
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from digests import code_digests, pair_digests, pair_offsets  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _say(msg):
     print(msg, flush=True)
+
+
+def _golden(name):
+    return np.load(os.path.join(GOLDEN, f"fullsize_{name}.npz"))
 
 
 def _dev_flat(images):
@@ -30,77 +46,43 @@ def _dev_flat(images):
     return [flat[offs[i]:offs[i + 1]] for i in range(len(images))]
 
 
-def _pair_offsets(images, pairs):
-    nq = np.array([images[q].shape[0] for q in pairs[:, 0]], np.int64)
-    return np.concatenate([[0], np.cumsum(nq)])
+def _check_codes(g, codes, keys, tag):
+    c = [x.cpu().numpy().view(np.uint64) if hasattr(x, "cpu") else x for x in codes]
+    k = [x.cpu().numpy() if hasattr(x, "cpu") else x for x in keys]
+    bad = np.flatnonzero(code_digests(c, k) != g["code_digest"])
+    assert len(bad) == 0, f"{tag}: codes or keys of {len(bad)} images differ from the oracle, first {bad[:8]}"
 
 
-def _check_sampled(w, S, N, mats, got, sample_pairs, n_q_per_pair, rng, **kw):
-    """Oracle on sampled (pair, query) outputs.  Codes of the sampled images
-    come from the oracle itself (column sums over the whole set)."""
-    off = _pair_offsets(w.images, w.pairs)
-    cache = {}
-
-    def codes(m):
-        if m not in cache:
-            cache[m] = oracle.project(w.images[m], S, N, *mats)
-        return cache[m]
-
-    checked = 0
-    for p in sample_pairs:
-        qi, ti = (int(x) for x in w.pairs[p])
-        nq = w.images[qi].shape[0]
-        if nq == 0:
-            continue
-        sel = np.sort(rng.choice(nq, size=min(nq, n_q_per_pair), replace=False)).astype(np.int32)
-        cq, kq = codes(qi)
-        ct, kt = codes(ti)
-        extra = {}
-        if "F" in kw:
-            extra = dict(kp_q=w.kp[qi], kp_t=w.kp[ti], F=w.F[p], max_px=kw["max_px"])
-        exp = oracle.match_pair(w.images[qi], cq, kq, w.images[ti], ct, kt, k=10, q_idx=sel, **extra)
-        for g, e, name in zip(got, exp, ("match_idx", "d1sq", "d2sq")):
-            gv = g[off[p] + sel]
-            bad = np.flatnonzero(gv != e)
-            assert len(bad) == 0, f"pair {p} ({qi},{ti}) {name}: {len(bad)} differ, e.g. q={sel[bad[:3]]} {gv[bad[:3]]} vs {e[bad[:3]]}"
-        checked += len(sel)
-    return checked
+def _check_pairs(g, w, got, tag):
+    got = [x.cpu().numpy() if hasattr(x, "cpu") else np.asarray(x) for x in got]
+    assert len(got[0]) == int(g["n_queries"])
+    d = pair_digests(*got, pair_offsets(w.n_feat, w.pairs))
+    bad = np.flatnonzero(d != g["pair_digest"])
+    assert len(bad) == 0, (f"{tag}: {len(bad)} of {len(d)} pairs differ from the oracle, first "
+                           f"{[(int(p), tuple(int(x) for x in w.pairs[p])) for p in bad[:6]]}")
+    assert int((got[0] >= 0).sum()) == int(g["n_matches"])
+    _say(f"{tag}: all {len(d)} pairs equal the oracle ({int(g['n_matches'])} matches)")
+    return got
 
 
 def test_scenes_full_size_bench_configuration():
     _say("full size: scenes 100 x 8000, 4950 pairs (bench configuration)")
+    g = _golden("scenes")
     w = synth.scene_set()
     mats = synth.projection_matrices()
     d = _dev_flat(w.images)
     m = binding.Matcher(*mats, mode="batched", mem="device")
     codes, keys, st = m.build_codes(d)
-    oc, ok = oracle.build_codes(w.images, *mats)
-    for i in range(len(w.images)):
-        assert np.array_equal(codes[i].cpu().numpy().view(np.uint64), oc[i]), f"codes of image {i}"
-        assert np.array_equal(keys[i].cpu().numpy(), ok[i]), f"keys of image {i}"
+    _check_codes(g, codes, keys, "batched codes")
     _say(f"codes equal; near-margin recomputes {st['near_margin_recomputes']}")
     got, stm = m.match_pairs(d, codes, keys, w.pairs)
-    got = [g.cpu().numpy() for g in got]
-    S, N = oracle.column_sums(w.images)
-    rng = np.random.default_rng(0)
-    sample = rng.choice(len(w.pairs), size=40, replace=False)
-    n = _check_sampled(w, S, N, mats, got, sample, 400, rng)
-    # two pairs in full
-    for p in sample[:2]:
-        qi, ti = w.pairs[p]
-        exp = oracle.match_pair(w.images[qi], oc[qi], ok[qi], w.images[ti], oc[ti], ok[ti], k=10)
-        off = _pair_offsets(w.images, w.pairs)
-        for g, e in zip(got, exp):
-            assert np.array_equal(g[off[p]:off[p + 1]], e)
-    _say(f"sampled {n} queries equal the oracle")
-    # the plain per-pair form gives identical outputs
+    _check_pairs(g, w, got, "batched")
+    # the plain per-pair form (fp32 projection, one launch per pair)
     mp = binding.Matcher(*mats, mode="plain", mem="device")
     cp, kp, _ = mp.build_codes(d)
-    for i in range(len(w.images)):
-        assert torch.equal(cp[i], codes[i]) and torch.equal(kp[i], keys[i])
+    _check_codes(g, cp, kp, "plain codes")
     gp, _ = mp.match_pairs(d, cp, kp, w.pairs)
-    for a, b in zip(got, gp):
-        assert np.array_equal(a, b.cpu().numpy())
+    _check_pairs(g, w, gp, "plain")
 
 
 @pytest.fixture(scope="module")
@@ -111,57 +93,46 @@ def uneven():
 
 def test_uneven_full_size_device_and_streamed(uneven):
     w = uneven
+    g = _golden("uneven")
     mats = synth.projection_matrices()
     nf = w.n_feat
     assert nf.min() >= 1000 and nf.max() <= 20000 and len(w.pairs) == 60000
     d = _dev_flat(w.images)
     m = binding.Matcher(*mats, mode="batched", mem="device")
     codes, keys, st = m.build_codes(d)
+    _check_codes(g, codes, keys, "uneven device codes")
     got, stm = m.match_pairs(d, codes, keys, w.pairs)
-    got = [g.cpu().numpy() for g in got]
     _say(f"device mode done: {stm['queries']} queries, {stm['ms_match']:.1f} ms")
-    S, N = oracle.column_sums(w.images)
-    rng = np.random.default_rng(1)
-    # codes of sampled images in full
-    for i in rng.choice(len(w.images), size=12, replace=False):
-        c, k = oracle.project(w.images[i], S, N, *mats)
-        assert np.array_equal(codes[i].cpu().numpy().view(np.uint64), c) and np.array_equal(keys[i].cpu().numpy(), k)
-    # the largest and smallest pairs are in the sample
-    cost = nf[w.pairs[:, 0]].astype(np.int64) * nf[w.pairs[:, 1]]
-    sample = np.concatenate([[np.argmax(cost), np.argmin(cost)], rng.choice(len(w.pairs), size=30, replace=False)])
-    n = _check_sampled(w, S, N, mats, got, sample, 300, rng)
-    _say(f"sampled {n} queries equal the oracle")
+    _check_pairs(g, w, got, "uneven device")
     # host-memory mode: numpy inputs streamed in scheduled blocks
-    del d, codes, keys
+    del d, codes, keys, got
     torch.cuda.empty_cache()
     mh = binding.Matcher(*mats, mode="batched", mem="host", device_budget_bytes=3 << 30)
     hcodes, hkeys, sth = mh.build_codes(w.images)
+    _check_codes(g, hcodes, hkeys, "uneven host codes")
     goth, sth2 = mh.match_pairs(w.images, hcodes, hkeys, w.pairs)
     _say(f"host mode: {sth2['image_loads']} image loads, {sth2['h2d_bytes'] / 1e9:.2f} GB up, "
          f"{sth2['ms_match']:.0f} ms")
     assert sth2["image_loads"] > len(w.images)
-    for a, b in zip(got, goth):
-        assert np.array_equal(a, b)
+    _check_pairs(g, w, goth, "uneven host")
 
 
 def test_epipolar_full_size():
     _say("generating epipolar set: 500 images x 12000, 15000 pairs")
+    g = _golden("epipolar")
     w = synth.epipolar_set()
+    assert float(g["max_px"]) == w.max_px
     mats = synth.projection_matrices()
     d = _dev_flat(w.images)
     kp = _dev_flat(w.kp)
     m = binding.Matcher(*mats, mode="batched", mem="device")
     codes, keys, _ = m.build_codes(d)
+    _check_codes(g, codes, keys, "epipolar codes")
     got, st = m.match_pairs_epipolar(d, codes, keys, kp, w.pairs, w.F, w.max_px)
-    got = [g.cpu().numpy() for g in got]
     _say(f"epipolar: {st['queries']} queries, union/bucket = {st['union_size'] / st['bucket_entries']:.3f}, "
          f"{st['ms_match']:.1f} ms")
     assert st["union_size"] < 0.2 * st["bucket_entries"]
-    S, N = oracle.column_sums(w.images)
-    rng = np.random.default_rng(2)
-    sample = rng.choice(len(w.pairs), size=30, replace=False)
-    n = _check_sampled(w, S, N, mats, got, sample, 400, rng, F=True, max_px=w.max_px)
-    _say(f"sampled {n} queries equal the oracle")
+    _check_pairs(g, w, got, "epipolar")
 
 
 def test_geometric_full_size():

@@ -457,3 +457,40 @@ def test_autotune_cache_file_and_fixed_shape(mats, monkeypatch, tmp_path):
     got3, st3 = m3.match_pairs(dimgs, codes, keys, w.pairs)
     for a, b, c in zip(ref, got, got3):
         assert np.array_equal(a, b.cpu().numpy()) and np.array_equal(a, c.cpu().numpy())
+
+
+# ------------------------------------------------------------------ stream order
+
+def test_inputs_written_by_queued_torch_work(mats):
+    """A context made without a stream runs on its own stream, yet follows
+    the caller's default stream: inputs whose writes are still queued there
+    behind slow work are read only after those writes (codes, then matches,
+    equal the oracle)."""
+    w = synth.single_pair(n=900, n_shared=500)
+    oc, ok = oracle.build_codes(w.images, *mats)
+    exp = _oracle_all(w.images, oc, ok, w.pairs, k=10)
+    m = binding.Matcher(*mats)
+    src = _dev(w.images)
+    dst = [torch.zeros_like(s) for s in src]
+    torch.cuda.synchronize()
+
+    def slow():
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(12):
+            a = a @ a
+            a = a / a.abs().max()
+        return a
+
+    slow()
+    for s, d in zip(src, dst):
+        d.copy_(s)  # queued behind the products on the default stream
+    codes, keys, _ = m.build_codes(dst)
+    _assert_codes(codes, keys, oc, ok, "codes after queued writes")
+    c2 = [torch.zeros_like(c) for c in codes]
+    k2 = [torch.zeros_like(k) for k in keys]
+    torch.cuda.synchronize()
+    slow()
+    for a, b in zip(c2 + k2, list(codes) + list(keys)):
+        a.copy_(b)
+    got, _ = m.match_pairs(dst, c2, k2, w.pairs)
+    _assert_match(got, exp, "matches after queued writes")
