@@ -9,8 +9,16 @@ before timing; outputs stay in HBM.  Prints ONE JSON line on stdout;
 progress goes to stderr.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu] [--no-plain]
-                  [--tau-sweep] [--geometric]
+                  [--no-legs] [--tau-sweep] [--geometric] [--disk MB]
 
+Besides the headline, the default run measures (each as its own object):
+  host_buffers : the same set and pairs with host-memory inputs and outputs
+                 (uploads, kernels and downloads; codes prebuilt);
+  uneven       : 2000 images of 1000-20000 features, 60000 pairs, streamed
+                 from host memory in the scheduler's load order under a
+                 3 GB device budget, and with the whole set resident;
+  epipolar     : 500 images x 12000 features, 15000 pairs, 4 px band around
+                 the true fundamental matrices (device memory).
 --geometric adds the two-stage geometry-aware form (top-scale subset
 matching, RANSAC fundamental matrices, guided matching of accepted pairs) on
 2 scenes x 250 cameras x 12000 features with 15000 pairs, against unguided
@@ -31,18 +39,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one full matcher launch on this workload, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy (x2.0 and x1.0); see
-# profiles/match_kernel_scenes_100x8000.md.  Valid only for the matcher
-# sources they were taken on (sha256 over MATCHER_SOURCES, in order).
+# Counters of one full matcher launch on the headline workload, from
+# rocprofv3 --pmc runs (profiles/match_kernel_scenes_100x8000.md): HBM bytes
+# from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (x2.0 and x1.0), and
+# SQ_INSTS_VALU.  Valid only for the matcher sources they were taken on
+# (sha256 over MATCHER_SOURCES, in order); null otherwise.
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_TRAFFIC = {"sources_sha256": "7a66e258b8c437551b41b488a3763f60b0dbb83105040317a1412adab5bfcb8a",
-                    "workload": "scenes_100x8000_exhaustive_4950pairs",
-                    "fetch_bytes": int(4298799.8 * 1024 * 2), "write_bytes": int(479093.1 * 1024),
-                    # rocprofv3 --pmc SQ_INSTS_VALU: wavefront VALU instructions of one launch
-                    "valu_insts": 9139892569}
+MEASURED_COUNTERS = {"sources_sha256": "7a66e258b8c437551b41b488a3763f60b0dbb83105040317a1412adab5bfcb8a",
+                     "workload": "scenes_100x8000_exhaustive_4950pairs",
+                     "fetch_bytes": int(4298799.8 * 1024 * 2), "write_bytes": int(479093.1 * 1024),
+                     "valu_insts": 9139892569}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
-# every 4 cycles, 2.4 GHz
+# every 4 cycles (16 lanes per cycle), 2.4 GHz: 614.4 G instructions/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
@@ -54,22 +62,43 @@ def matcher_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    t = MEASURED_TRAFFIC
+def measured_counters(workload):
+    t = MEASURED_COUNTERS
     if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    return t
 
 
-def measured_valu_issue(workload, kernel_ms):
-    """Counted VALU instructions of the matcher over what the SIMDs can issue
-    in its measured time (null once the sources changed)."""
-    t = MEASURED_TRAFFIC
-    if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
-        return None
-    return {"valu_insts": t["valu_insts"],
-            "frac": round(t["valu_insts"] / (VALU_ISSUE_PEAK * kernel_ms * 1e-3), 4),
-            "note": "SQ_INSTS_VALU of one launch / (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction x kernel time)"}
+def roofline(workload, kernel_ms, stats):
+    """The matcher against the limit that binds it, VALU issue (counted
+    instructions over what the SIMDs issue in the measured kernel time), with
+    its measured HBM traffic against the HBM peak and the method's touched
+    bytes (which exceed HBM bandwidth because they are re-read from L2/LDS)
+    as separate fields."""
+    t = measured_counters(workload)
+    sec = kernel_ms * 1e-3
+    abytes = algorithmic_bytes(stats)
+    out = {"bound": "alu", "kernel": "match_kernel<false, 4, false>", "kernel_ms": round(kernel_ms, 4),
+           "unit": "G VALU wave64 instructions/s", "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+           "achieved": None, "frac": None, "traffic": None,
+           "hbm": None,
+           "touched_bytes": {"bytes_per_launch": int(abytes), "GB_per_s": round(abytes / sec / 1e9, 1),
+                             "vs_hbm_peak": round(abytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+                             "note": "the method's bytes per query (codes, bucket indices, kept ids, descriptors, "
+                                     "outputs) x queries / kernel time; above the HBM peak because the train "
+                                     "tables are re-read from L2 and LDS, not HBM (cache reuse, not a roofline)"},
+           "note": ("bound = VALU issue: SQ_INSTS_VALU of one launch / (1024 SIMDs x 2.4 GHz / 4 cycles per wave64 "
+                    "instruction) / kernel time; traffic = HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                    "copy-scaled); counters from profiles/, null once the matcher sources change")}
+    if t is not None:
+        insts = t["valu_insts"]
+        traffic = t["fetch_bytes"] + t["write_bytes"]
+        out.update(achieved=round(insts / sec / 1e9, 1), frac=round(insts / sec / VALU_ISSUE_PEAK, 4),
+                   traffic=traffic, valu_insts_per_launch=insts,
+                   valu_insts_per_query=round(insts / stats["queries"], 1))
+        out["hbm"] = {"achieved": round(traffic / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def log(msg):
@@ -122,6 +151,7 @@ def cpu_baseline(w, mats, budget_s=20.0):
     per_pair = t_match / len(sample_pairs)
     step_s = t_colsum + per_img * len(imgs) + per_pair * len(pairs)
     return {"value": len(pairs) / step_s, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(),
             "sample": (f"column sums of all {len(imgs)} images ({t_colsum:.2f}s), codes of {n_img_sample} images "
                        f"({per_img * 1e3:.0f} ms/image), matching of {len(sample_pairs)} of {len(pairs)} pairs "
                        f"({per_pair * 1e3:.0f} ms/pair); step time extrapolated to all images and pairs: "
@@ -207,6 +237,116 @@ def geometric_leg(binding, synth, torch, steps, cpu_seconds, no_cpu):
     return out
 
 
+def _median_calls(fn, n):
+    """Median wall time (s) of n calls of fn (each returns after its outputs
+    are complete), and the last call's return value."""
+    ts, r = [], None
+    for _ in range(n):
+        t0 = time.perf_counter()
+        r = fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), r
+
+
+def host_buffers_leg(binding, w, mats, reps=5):
+    """The headline set and pairs with host-memory inputs and outputs: the
+    library uploads descriptors, codes and keys through pinned staging, runs
+    the matcher and copies the outputs back into the caller's numpy arrays.
+    Codes are prebuilt (reported separately); 1 warm-up call, median of reps."""
+    m = binding.Matcher(*mats, mode="batched", mem="host")
+    imgs = m.bind(w.images, np.uint8)
+    t0 = time.perf_counter()
+    codes, keys, stc = m.build_codes(imgs)
+    t_codes = time.perf_counter() - t0
+    b_codes, b_keys = m.bind(codes), m.bind(keys)
+    n_q = w.n_queries
+    outs = tuple(np.empty(n_q, np.int32) for _ in range(3))
+    m.match_pairs(imgs, b_codes, b_keys, w.pairs, out=outs)
+    dt, (_, st) = _median_calls(lambda: m.match_pairs(imgs, b_codes, b_keys, w.pairs, out=outs), reps)
+    m.close()
+    P = len(w.pairs)
+    return {"workload": f"scenes_{len(w.images)}x{int(w.n_feat[0])}_exhaustive_{P}pairs_host_buffers",
+            "pairs_per_s": round(P / dt, 1), "ms_per_call_median": round(dt * 1e3, 3), "calls": reps,
+            "h2d_bytes": st["h2d_bytes"], "d2h_bytes": st["d2h_bytes"], "image_loads": st["image_loads"],
+            "ms_codes_host": round(t_codes * 1e3, 3), "matches": int((outs[0] >= 0).sum()),
+            "note": "wall time of cashash_match_pairs with host inputs and outputs (uploads + kernels + downloads)"}
+
+
+def uneven_leg(binding, synth, mats, reps=3):
+    """2000 images of 1000-20000 features (log-uniform), 30 partners each:
+    60000 pairs in host memory, matched by the library in its scheduled load
+    order, under a 3 GB device budget (blocks streamed and reloaded) and with
+    the default budget (the whole set resident)."""
+    t0 = time.perf_counter()
+    w = synth.uneven_set()
+    log(f"uneven: generated {len(w.images)} images ({int(w.n_feat.sum())} features), {len(w.pairs)} pairs "
+        f"in {time.perf_counter() - t0:.1f}s")
+    P = len(w.pairs)
+    out = {"workload": f"uneven_{len(w.images)}_1k-20k_{P}pairs", "n_features": int(w.n_feat.sum()),
+           "queries": w.n_queries}
+    outs = tuple(np.empty(w.n_queries, np.int32) for _ in range(3))
+    ref = None
+    for tag, budget in (("streamed_3GB", 3 << 30), ("resident", 0)):
+        m = binding.Matcher(*mats, mode="batched", mem="host", device_budget_bytes=budget)
+        imgs = m.bind(w.images, np.uint8)
+        t0 = time.perf_counter()
+        codes, keys, stc = m.build_codes(imgs)
+        t_codes = time.perf_counter() - t0
+        b_codes, b_keys = m.bind(codes), m.bind(keys)
+        m.match_pairs(imgs, b_codes, b_keys, w.pairs, out=outs)       # tunes
+        dt, (_, st) = _median_calls(lambda: m.match_pairs(imgs, b_codes, b_keys, w.pairs, out=outs), reps)
+        got = int((outs[0] >= 0).sum())
+        ref = got if ref is None else ref
+        out[tag] = {"device_budget_bytes": budget, "pairs_per_s": round(P / dt, 1),
+                    "ms_per_call_median": round(dt * 1e3, 2), "calls": reps, "h2d_bytes": st["h2d_bytes"],
+                    "d2h_bytes": st["d2h_bytes"], "image_loads": st["image_loads"],
+                    "ms_codes_host": round(t_codes * 1e3, 2), "codes_image_loads": stc["image_loads"],
+                    "matches": got, "same_matches_as_streamed": got == ref}
+        log(f"uneven {tag}: {out[tag]}")
+        m.close()
+    return out
+
+
+def epipolar_leg(binding, synth, torch, mats, reps=5):
+    """500 images x 12000 features, 15000 neighbour pairs, candidates kept
+    within 4 px of the epipolar line of the true fundamental matrix (Eq. 1-2);
+    device memory, codes prebuilt; the band kernel's own time from hipEvents."""
+    t0 = time.perf_counter()
+    w = synth.epipolar_set()
+    log(f"epipolar: generated in {time.perf_counter() - t0:.1f}s")
+
+    def dev(arrs):
+        flat = torch.from_numpy(np.concatenate(arrs)).cuda()
+        offs = np.concatenate([[0], np.cumsum([len(a) for a in arrs])])
+        return [flat[offs[i]:offs[i + 1]] for i in range(len(arrs))]
+
+    m = binding.Matcher(*mats, mode="batched", mem="device")
+    d, kp = m.bind(dev(w.images)), m.bind(dev(w.kp))
+    codes, keys, _ = m.build_codes(d)
+    b_codes, b_keys = m.bind(codes), m.bind(keys)
+    outs = tuple(torch.empty(w.n_queries, dtype=torch.int32, device="cuda") for _ in range(3))
+    m.match_pairs_epipolar(d, b_codes, b_keys, kp, w.pairs, w.F, w.max_px, out=outs)   # tunes
+    torch.cuda.synchronize()
+    kms = []
+
+    def call():
+        r = m.match_pairs_epipolar(d, b_codes, b_keys, kp, w.pairs, w.F, w.max_px, out=outs)
+        kms.append(m.last_kernel_ms()[0])
+        return r
+
+    dt, (_, st) = _median_calls(call, reps)
+    P = len(w.pairs)
+    res = {"workload": f"epipolar_500x12000_{P}pairs_band4px", "pairs_per_s": round(P / dt, 1),
+           "ms_per_call_median": round(dt * 1e3, 3), "kernel": "match_kernel<true, 4, true>",
+           "kernel_ms_median": round(float(np.median(kms)), 3), "calls": reps,
+           "bucket_entries_per_query": round(st["bucket_entries"] / st["queries"], 2),
+           "band_survivors_per_query": round(st["union_size"] / st["queries"], 2),
+           "matches": int((outs[0] >= 0).sum().item())}
+    m.close()
+    return res
+
+
+
 def disk_leg(binding, w, mats, budget_bytes):
     """The three-level path on the bench set: set file on local disk, codes
     and matches streamed through host groups of budget_bytes / 3."""
@@ -245,6 +385,8 @@ def main():
     ap.add_argument("--feats", type=int, default=8000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the host-buffer, uneven (streamed) and epipolar legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tau-sweep", action="store_true",
                     help="also match with Hamming thresholds tau in 128..32 (ranking section) and report matches/time")
@@ -298,7 +440,7 @@ def main():
     codes_buf = [torch.empty((n, 2), dtype=torch.int64, device="cuda") for n in nf]
     keys_buf = [torch.empty((n, 6), dtype=torch.uint8, device="cuda") for n in nf]
 
-    def run(m, n_steps, tag):
+    def run(m, n_steps, tag, quiet=False):
         st_codes = st_match = None
         kernel_ms, launches = [], 0
         # buffer lists marshalled once, as a caller making repeated calls would
@@ -312,38 +454,35 @@ def main():
             kernel_ms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
-        log(f"{tag}: {n_steps} steps in {dt:.3f}s -> {n_pairs * n_steps / dt:.1f} pairs/s")
-        return dt, st_codes, st_match, kernel_ms, launches
+        if not quiet:
+            log(f"{tag}: {n_steps} steps in {dt:.3f}s -> {n_pairs * n_steps / dt:.1f} pairs/s")
+        return dt, st_codes, st_match, kernel_ms, launches, dt / n_steps
 
     m = binding.Matcher(*mats, mode="batched", mem="device")
     log("warmup (batched bf16x2)")
     run(m, args.warmup, "warmup")
-    dt, st_codes, st_match, kms, launches = run(m, args.steps, "batched")
+    dt, st_codes, st_match, kms, launches, _ = run(m, args.steps, "batched")
     value = n_pairs * args.steps / dt
     ms_step = dt * 1e3 / args.steps
     kernel_ms = float(np.mean(kms))
     ref = [o.cpu().numpy() for o in outs]
 
-    abytes = algorithmic_bytes(st_match)
-    achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    workload = f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"
+    # per-step times: median of 5 single steps, each synchronised (host clock)
+    step_ms = []
+    for _ in range(5):
+        _, _, _, _, _, dts = run(m, 1, "median step", quiet=True)
+        step_ms.append(dts * 1e3)
     result = {
         "metric": "image pairs matched/sec at 8k feats/image (batched bf16-split vs plain fp32)",
         "value": round(value, 2), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16x2-mfma+u8/int32", "data": "synthetic",
-        "config": {"workload": f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs",
+        "config": {"workload": workload,
                    "n_images": args.images, "n_feat": args.feats, "pairs": n_pairs, "k": 10, "ratio": 0.8,
                    "form": "batched bf16 hi+lo MFMA projection, one persistent matcher launch"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs"),
-                     "kernel": "match_kernel<false, 4, false>", "kernel_ms": round(kernel_ms, 4),
-                     "valu_issue": measured_valu_issue(
-                         f"scenes_{args.images}x{args.feats}_exhaustive_{n_pairs}pairs", kernel_ms),
-                     "note": ("achieved = algorithmic (touched) bytes of the byte model / kernel time; "
-                              "frac > 1 means the working set is re-read from L2/LDS (cache reuse); "
-                              "traffic = measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)"),
-                     "algorithmic_bytes_per_launch": int(abytes)},
+        "roofline": roofline(workload, kernel_ms, st_match),
+        "step_ms_median_of_5": round(float(np.median(step_ms)), 3),
         "stats": {"near_margin_recomputes": st_codes["near_margin_recomputes"],
                   "bucket_entries_per_query": round(st_match["bucket_entries"] / st_match["queries"], 2),
                   "union_per_query": round(st_match["union_size"] / st_match["queries"], 2),
@@ -355,7 +494,7 @@ def main():
     if not args.no_plain:
         mp = binding.Matcher(*mats, mode="plain", mem="device")
         run(mp, 1, "plain warmup")
-        dtp, _, _, kmsp, lp = run(mp, max(1, min(args.steps, 2)), "plain")
+        dtp, _, _, kmsp, lp, _ = run(mp, max(1, min(args.steps, 2)), "plain")
         plain_value = n_pairs * max(1, min(args.steps, 2)) / dtp
         same = all(np.array_equal(a, o.cpu().numpy()) for a, o in zip(ref, outs))
         result["plain_fp32_per_pair"] = {"value": round(plain_value, 2), "unit": "pairs/s",
@@ -379,6 +518,13 @@ def main():
             mt.close()
         result["tau_sweep"] = sweep
     m.close()
+    if not args.no_legs:
+        log("host-buffer leg")
+        result["host_buffers"] = host_buffers_leg(binding, w, mats)
+        log(f"host buffers: {result['host_buffers']}")
+        result["uneven"] = uneven_leg(binding, synth, mats)
+        result["epipolar"] = epipolar_leg(binding, synth, torch, mats)
+        log(f"epipolar: {result['epipolar']}")
     if args.disk:
         log(f"disk level, host budget {args.disk} MB")
         result["disk"] = disk_leg(binding, w, mats, args.disk << 20)
