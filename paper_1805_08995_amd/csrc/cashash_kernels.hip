@@ -295,9 +295,13 @@ __global__ __launch_bounds__(256) void proj_fp32_kernel(const ImgDev* __restrict
 // Binary64 recompute of near-margin projections: the same fused
 // multiply-add chain over components 0..127 of r_j . (N x - S) that defines
 // the codes; N x_i - S_i is an exact integer in binary64.  One wavefront per
-// segment of the near list (grid-stride), one lane per listed descriptor; it
-// is the only writer of that code.  The recompute count is reduced over the
-// block and added with one atomic per block.
+// segment of the near list (grid-stride).  The (descriptor, row) recomputes
+// of up to 64 listed descriptors are spread over the lanes 64 at a time,
+// whichever descriptor they belong to, so a descriptor with many flagged
+// rows does not hold its lane for all of them; their bits are OR-ed into
+// per-descriptor words in LDS, and the lane that read a descriptor's entry
+// then ORs them into its code and keys (the only writer of that code).  The
+// recompute count is reduced over the block and added with one atomic.
 __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ imgs,
                                                     const CodeOut* __restrict__ outs,
                                                     const NearEntry* __restrict__ near,
@@ -305,43 +309,102 @@ __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ i
                                                     uint32_t n_seg, const double* __restrict__ R,
                                                     const unsigned long long* __restrict__ S, double n_tot,
                                                     unsigned long long* __restrict__ counter) {
+    __shared__ double s_S[kDim];
+    __shared__ uint32_t s_pre[4][64];                 // per wave: inclusive prefix of recomputes per entry
+    __shared__ unsigned long long s_bits[4][64][3];   // per wave and entry: recomputed bits
     __shared__ uint32_t s_cnt[4];
+    for (int i = threadIdx.x; i < kDim; i += blockDim.x) s_S[i] = (double)S[i];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
     uint32_t cnt = 0;
-    for (uint32_t sg = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); sg < n_seg; sg += n_waves)
-    for (uint32_t i = lane, ns = seg_count[sg]; i < ns; i += 64) {
-        const NearEntry e = near[(size_t)sg * seg_cap + i];
-        const CodeOut o = outs[e.img];
-        const int64_t row = e.row;
-        uint64_t mk[3] = {e.mask[0], e.mask[1], e.mask[2]};
-        cnt += (uint32_t)(__popcll(mk[0]) + __popcll(mk[1]) + __popcll(mk[2]));
-        const uint8_t* x = imgs[e.img].desc + row * kDim;
-        uint64_t wd[3] = {o.codes[2 * row], o.codes[2 * row + 1], 0};
+    for (uint32_t sg = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); sg < n_seg; sg += n_waves) {
+        const uint32_t ns = uniform(seg_count[sg]);
+        for (uint32_t base = 0; base < ns; base += 64) {
+            const uint32_t i = base + (uint32_t)lane;
+            const bool has = i < ns;
+            NearEntry e{};
+            if (has) e = near[(size_t)sg * seg_cap + i];
+            const uint32_t pc = has ? (uint32_t)(__popcll(e.mask[0]) + __popcll(e.mask[1]) + __popcll(e.mask[2])) : 0u;
+            const uint32_t incl = wave_incl_scan(pc, lane);
+            const uint32_t total = uniform(__shfl(incl, 63));
+            s_pre[wv][lane] = incl;
+            s_bits[wv][lane][0] = s_bits[wv][lane][1] = s_bits[wv][lane][2] = 0ull;
+            wave_sync();
+            cnt += total;
+            for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+                const uint32_t j = j0 + (uint32_t)lane;
+                const bool act = j < total;
+                // owner: the first entry whose inclusive prefix exceeds j
+                uint32_t L = 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            while (mk[k]) {
-                const int bitpos = __ffsll((unsigned long long)mk[k]) - 1;
-                mk[k] &= mk[k] - 1;
-                const int r = 64 * k + bitpos;
-                const double* rr = R + r * kDim;
-                double p = 0.0;
-                for (int i = 0; i < kDim; ++i) {
-                    const double c = n_tot * (double)x[i] - (double)S[i];
-                    p = fma(rr[i], c, p);
+                for (uint32_t step = 32; step >= 1; step >>= 1)
+                    if (s_pre[wv][L + step - 1] <= j) L += step;
+                L = act ? L : 0u;
+                const uint32_t start = L ? s_pre[wv][L - 1] : 0u;
+                uint32_t kth = act ? j - start : 0u;
+                const uint64_t m0 = __shfl(e.mask[0], (int)L), m1 = __shfl(e.mask[1], (int)L),
+                               m2 = __shfl(e.mask[2], (int)L);
+                const int img = __shfl(e.img, (int)L), row = __shfl(e.row, (int)L);
+                // the kth set bit of the owner's 176-bit mask
+                int word = 0;
+                uint64_t w = m0;
+                const uint32_t c0 = (uint32_t)__popcll(m0), c1 = (uint32_t)__popcll(m1);
+                if (kth >= c0) {
+                    kth -= c0;
+                    word = 1;
+                    w = m1;
+                    if (kth >= c1) {
+                        kth -= c1;
+                        word = 2;
+                        w = m2;
+                    }
                 }
-                if (p > 0.0) wd[k] |= (uint64_t)1 << bitpos;
+                for (uint32_t t = 0; t < kth; ++t) w &= w - 1;
+                const int bitpos = w ? __ffsll((unsigned long long)w) - 1 : 0;
+                if (act) {
+                    const int r = 64 * word + bitpos;
+                    const uint4* xp = reinterpret_cast<const uint4*>(imgs[img].desc + (int64_t)row * kDim);
+                    const double2* rr = reinterpret_cast<const double2*>(R + r * kDim);
+                    double p = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const uint4 xv = gload(xp + q);
+                        const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const double2 r01 = rr[8 * q + 2 * a], r23 = rr[8 * q + 2 * a + 1];
+                            const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
+#pragma unroll
+                            for (int bb = 0; bb < 4; ++bb) {
+                                const int ci = 16 * q + 4 * a + bb;
+                                const double c = n_tot * (double)((xw[a] >> (8 * bb)) & 0xFFu) - s_S[ci];
+                                p = fma(rv[bb], c, p);
+                            }
+                        }
+                    }
+                    if (p > 0.0) atomicOr(&s_bits[wv][L][word], 1ull << bitpos);
+                }
             }
-        }
-        o.codes[2 * row] = wd[0];
-        o.codes[2 * row + 1] = wd[1];
-        if (wd[2]) {
-            uint8_t* kb = o.keys + 6 * row;
-            for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((wd[2] >> (8 * tb)) & 0xFFu));
+            wave_sync();
+            if (has && pc) {
+                const CodeOut o = outs[e.img];
+                const int64_t row = e.row;
+                const uint64_t b0 = s_bits[wv][lane][0], b1 = s_bits[wv][lane][1], b2 = s_bits[wv][lane][2];
+                if (b0 | b1) {
+                    o.codes[2 * row] |= b0;
+                    o.codes[2 * row + 1] |= b1;
+                }
+                if (b2) {
+                    uint8_t* kb = o.keys + 6 * row;
+                    for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((b2 >> (8 * tb)) & 0xFFu));
+                }
+            }
+            wave_sync();  // s_pre and s_bits are rewritten by the next batch
         }
     }
-    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
-    if (lane == 0) s_cnt[threadIdx.x >> 6] = cnt;
+    if (lane == 0) s_cnt[wv] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
