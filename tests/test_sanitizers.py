@@ -1,8 +1,8 @@
-"""Host code under sanitizers (no device): the CPU oracle and the block
-scheduler of host-memory matching, each driven by a harness in
-tests/sanitize/ and built with gcc/g++ with AddressSanitizer and
-UndefinedBehaviorSanitizer.  A sanitizer report makes the harness exit
-non-zero."""
+"""Host code under sanitizers (no device): the CPU oracle, the block
+scheduler of host-memory matching and the host worker pool of the copies,
+each driven by a harness in tests/sanitize/ and built with gcc/g++ with
+AddressSanitizer and UndefinedBehaviorSanitizer (the pool also with
+ThreadSanitizer).  A sanitizer report makes the harness exit non-zero."""
 import os
 import shutil
 import subprocess
@@ -42,3 +42,15 @@ def test_scheduler_under_asan_ubsan(tmp_path):
                          [os.path.join(SAN, "sched_harness.cpp")], "sched_harness")
     assert "scheduler harness ok" in out
 
+
+
+def test_host_pool_under_asan_ubsan(tmp_path):
+    out = _build_and_run(tmp_path, "g++", ["-std=c++17", *ASAN_UBSAN],
+                         [os.path.join(SAN, "pool_harness.cpp"), "-lpthread"], "pool_harness_asan")
+    assert "pool harness ok" in out
+
+
+def test_host_pool_under_tsan(tmp_path):
+    out = _build_and_run(tmp_path, "g++", ["-std=c++17", "-O1", "-g", "-fsanitize=thread"],
+                         [os.path.join(SAN, "pool_harness.cpp"), "-lpthread"], "pool_harness_tsan")
+    assert "pool harness ok" in out
