@@ -163,6 +163,33 @@ int cashash_match_pairs_epipolar(cashash_ctx* ctx, const cashash_images* images,
                                  int32_t* match_idx, int32_t* d1sq, int32_t* d2sq,
                                  cashash_stats* stats);
 
+/* ---- Allocation-free matching ---------------------------------------------
+ * For callers that cannot allocate device memory during a call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Same arguments, outputs and errors as cashash_match_pairs, with
+ * cfg.mem == CASHASH_MEM_DEVICE.  Every device buffer of the call (bucket
+ * tables, uploaded image and pair tables, work items, work counters,
+ * statistics) is taken from one static device array of
+ * CASHASH_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds from
+ * its first context until the process ends; the call makes no device or
+ * pinned allocation (its planning uses ordinary host memory), runs its launch
+ * eagerly (no graph) with the cached or default launch shape (no tuning),
+ * and clears the counters it needs before use.  Scratch bytes used, each
+ * piece rounded up to 256:
+ *     sum over distinct train images t of (6*257*4 + 144*n_feat[t])
+ *   + 72*n_images + 4*n_train + 96*n_pairs + 16*tiles + 2048 + 64,
+ * tiles = sum over pairs of ceil(n_feat[query] / tile queries) (at most 32
+ * queries per tile).  A call needing more returns CASHASH_E_LIMIT before any
+ * device work.  All calls on one GPU share its array: calls that overlap in
+ * time on one GPU (from two threads or two contexts) race and must not be
+ * issued. */
+#define CASHASH_NOALLOC_SCRATCH_BYTES (32LL << 20)
+int cashash_match_pairs_noalloc(cashash_ctx* ctx, const cashash_images* images,
+                                const uint64_t* const* codes, const uint8_t* const* keys,
+                                int64_t n_pairs, const int32_t* pairs,
+                                int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats);
+
 /* Message for the last nonzero return on this thread ("" if none). */
 const char* cashash_last_error(void);
 

@@ -2,8 +2,11 @@
 
 Every step of the matching path runs in the library's HIP kernels.  PyTorch
 supplies device memory (tensors whose data pointers are passed through) and
-the stream (torch's current stream).  In host-memory mode numpy arrays are
-passed and the library streams them to the device itself.
+the stream: torch's current stream when the Matcher is made.  For torch's
+default stream (handle 0) the library runs on a stream of its own that waits,
+at every call, for the work already queued on the default stream.  In
+host-memory mode numpy arrays are passed and the library streams them to the
+device itself.
 
 The library must have been built (``python -m paper_1805_08995_amd.build`` or
 ``__graft_entry__.build()``); importing this module without it raises.
@@ -31,7 +34,8 @@ EXPORTED = ["cashash_default_config", "cashash_create", "cashash_set_config", "c
             "cashash_default_geometric_config", "cashash_subset_size", "cashash_select_top_scale",
             "cashash_gather_rows", "cashash_estimate_fundamental", "cashash_match_pairs_geometric",
             "cashash_last_geometric_ms", "cashash_set_write", "cashash_build_codes_disk",
-            "cashash_match_pairs_disk"]
+            "cashash_match_pairs_disk", "cashash_match_pairs_noalloc"]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 GEO_ACCEPT, GEO_FEW_MATCHES, GEO_DEGENERATE, GEO_FEW_INLIERS = 0, 1, 2, 3
 GEO_MAX_MATCHES = 8192
 
@@ -92,6 +96,7 @@ def lib():
         L.cashash_match_pairs.argtypes = [P, C.POINTER(Images), P, P, I64, P, P, P, P, C.POINTER(Stats)]
         L.cashash_match_pairs_epipolar.argtypes = [P, C.POINTER(Images), P, P, P, I64, P, P, C.c_double,
                                                    P, P, P, C.POINTER(Stats)]
+        L.cashash_match_pairs_noalloc.argtypes = [P, C.POINTER(Images), P, P, I64, P, P, P, P, C.POINTER(Stats)]
         L.cashash_last_error.restype = C.c_char_p
         L.cashash_plan_schedule.argtypes = [I32, P, I64, P, I64, P, P, P, P, P, I64, P]
         L.cashash_last_kernel_ms.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -111,6 +116,7 @@ def lib():
         L.cashash_match_pairs_disk.argtypes = [P, C.c_char_p, C.c_char_p, I64, P, C.c_char_p, C.c_char_p, I64, I64,
                                                C.POINTER(C.c_int64), C.POINTER(Stats)]
         for f in ("cashash_create", "cashash_set_config", "cashash_build_codes", "cashash_match_pairs",
+                  "cashash_match_pairs_noalloc",
                   "cashash_match_pairs_epipolar", "cashash_plan_schedule", "cashash_last_kernel_ms",
                   "cashash_select_top_scale", "cashash_gather_rows", "cashash_estimate_fundamental",
                   "cashash_match_pairs_geometric", "cashash_last_geometric_ms", "cashash_set_write",
@@ -311,6 +317,18 @@ class Matcher:
                                         *[(_dptr(a) if self.mem == "device" else (a.ctypes.data if a.size else None))
                                           for a in o], C.byref(stats)))
         return o, stats.as_dict()
+
+    def match_pairs_noalloc(self, images, codes, keys, pairs, out):
+        """match_pairs in the library's static device scratch (no device
+        allocation in the call); device memory only, out = (match_idx, d1sq,
+        d2sq) tensors the caller allocated."""
+        st, keep = self._images(images)
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        stats = Stats()
+        check(lib().cashash_match_pairs_noalloc(self.h, C.byref(st), self._arrays(codes), self._arrays(keys),
+                                                len(pairs), pairs.ctypes.data if len(pairs) else None,
+                                                *[_dptr(a) for a in out], C.byref(stats)))
+        return out, stats.as_dict()
 
     def match_pairs_epipolar(self, images, codes, keys, kp, pairs, F, max_px, out=None):
         st, keep = self._images(images)

@@ -22,6 +22,7 @@
 #include <unistd.h>
 
 #include <future>
+#include <mutex>
 #include <thread>
 
 #include "cashash.h"
@@ -191,6 +192,10 @@ struct cashash_ctx {
     // recorded on the caller's legacy default stream at each entry point when
     // the context runs on a stream of its own (cfg.stream == NULL)
     hipEvent_t caller_ev = nullptr;
+    // device address of this device's allocation-free scratch array (null if
+    // it could not be looked up; scratch_err says why)
+    uint8_t* scratch = nullptr;
+    std::string scratch_err;
 };
 
 static void quiesce(const cashash_ctx* c) {
@@ -337,6 +342,40 @@ extern "C" int cashash_set_config(cashash_ctx* c, const cashash_config* cfg) {
     return CASHASH_OK;
 }
 
+// ------------------------------------------------------------------ allocation-free scratch
+// The one device region of cashash_match_pairs_noalloc.  Every GPU the
+// library runs on holds its own copy at its own address until the process
+// ends.  In host code `scratch` only names the symbol: its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current,
+// at the first context created on it) and only that address is ever passed
+// to kernels or copies.
+static __device__ __align__(256) uint8_t scratch[CASHASH_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t* g_scratch_addr[kMaxDevices];
+static hipError_t g_scratch_rc[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+
+// Device address of `scratch` on `dev` (which must be the current device).
+static uint8_t* scratch_address(int dev, std::string& err) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        g_scratch_rc[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_addr[dev] = g_scratch_rc[dev] == hipSuccess ? static_cast<uint8_t*>(p) : nullptr;
+        g_scratch_done[dev] = true;
+    }
+    if (!g_scratch_addr[dev]) {
+        err = std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(g_scratch_rc[dev]);
+        hipGetLastError();  // do not leave the failure for the next call to report
+    }
+    return g_scratch_addr[dev];
+}
+
 extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const double* r_bucket,
                               const cashash_config* cfg) {
     if (!out || !r_code || !r_bucket) return fail(CASHASH_E_INVAL, "null argument to cashash_create");
@@ -365,6 +404,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess)
         return bail(fail(CASHASH_E_DEVICE, "hipGetDeviceProperties failed"));
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->scratch = scratch_address(c->device, c->scratch_err);
     {
         const char* g = std::getenv("CASHASH_GRAPHS");
         c->use_graphs = !(g && g[0] == '0');
@@ -674,6 +714,9 @@ struct MatchPlan {
     const PairDev* dP = nullptr;
     MatchParams prm{};
     std::vector<int64_t> order;
+    Item* items = nullptr;          // work items (items_cap of them)
+    int64_t items_cap = 0;
+    uint32_t* counter = nullptr;    // per-segment work counters of the persistent launch
 };
 
 // Segment boundaries (in items) that split the estimated cost (queries x
@@ -717,12 +760,13 @@ static int slots_for(const MatchJob& J, int64_t p) {
     return J.epi || n <= kLargeTrain ? 4 : n <= kHugeTrain ? 6 : 8;
 }
 
-// Generate the work items of shape qt on the device (into c->items).
-static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int qt, const PairTiles* dPT,
-                      int32_t n_pt, int64_t n_items) {
+// Generate the work items of shape qt on the device (into P.items, which
+// holds P.items_cap of them).
+static int make_items(cashash_ctx* c, const MatchPlan& P, int qt, const PairTiles* dPT, int32_t n_pt,
+                      int64_t n_items) {
     if (n_items > (int64_t)INT32_MAX) return fail(CASHASH_E_LIMIT, "too many query tiles in one call");
-    RETCHK(c->items.ensure((size_t)std::max<int64_t>(n_items, 1) * sizeof(Item)));
-    HIPCHK(launch_make_items(c->stream, dPT, n_pt, P.dP, P.dI, qt, c->items.as<Item>(), (int32_t)n_items));
+    if (n_items > P.items_cap) return fail(CASHASH_E_INVAL, "work item buffer too small");
+    HIPCHK(launch_make_items(c->stream, dPT, n_pt, P.dP, P.dI, qt, P.items, (int32_t)n_items));
     return CASHASH_OK;
 }
 
@@ -731,8 +775,8 @@ static int make_items(cashash_ctx* c, const MatchPlan& P, const MatchJob& J, int
 static int enqueue_matcher(cashash_ctx* c, const MatchPlan& P, MatchJob& J, Shape sh, bool batched,
                            const std::vector<int64_t>& first_of, int64_t n_pairs_run, int64_t n_items,
                            unsigned long long* stats, int64_t* launches, bool use_graph) {
-    uint32_t* counter = c->counters.as<uint32_t>();
-    const Item* items = c->items.as<Item>();
+    uint32_t* counter = P.counter;
+    const Item* items = P.items;
     if (batched) {
         // one persistent launch per register-slot group (pairs are ordered
         // small-train group first), each over its own item range
@@ -835,9 +879,41 @@ static int enqueue_matcher(cashash_ctx* c, const MatchPlan& P, MatchJob& J, Shap
     return CASHASH_OK;
 }
 
+// One caller-fixed device region that a match job carves its scratch out of
+// (bucket tables, uploaded tables, work items, counters, statistics) instead
+// of the context's growable buffers: the allocation-free entry point.
+struct ScratchArea {
+    uint8_t* base = nullptr;
+    size_t cap = 0, used = 0;
+    // the host copies of the uploaded tables, kept until the call ends (the
+    // uploads read pageable memory)
+    std::vector<std::vector<uint8_t>> host;
+    uint8_t* take(size_t n) {
+        const size_t o = (used + 255) & ~size_t(255);
+        if (o > cap || n > cap - o) return nullptr;
+        used = o + n;
+        return base + o;
+    }
+};
+
+// Uploads the Uploader's tables into the scratch area on c->stream.
+static int upload_scratch(cashash_ctx* c, ScratchArea& sa, Uploader& up, std::vector<const void*>& dptr) {
+    uint8_t* dst = sa.take(std::max<size_t>(up.host.size(), 1));
+    if (!dst) return fail(CASHASH_E_LIMIT, "the call needs more than the %zu-byte scratch", sa.cap);
+    sa.host.push_back(std::move(up.host));
+    const std::vector<uint8_t>& h = sa.host.back();
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(dst, h.data(), h.size(), hipMemcpyHostToDevice, c->stream));
+    dptr.clear();
+    for (size_t o : up.offs) dptr.push_back(dst + o);
+    return CASHASH_OK;
+}
+
 // Enqueues bucket tables and matcher launches for J on c->stream, plus the
 // read-back of the statistics into pinned memory; finish_match_job waits.
-static int launch_match_job(cashash_ctx* c, MatchJob& J) {
+// With a scratch area (sa) every device buffer of the job is taken from it,
+// the launch shape is the cached or default one (no tuning) and no graph is
+// captured, so nothing is allocated.
+static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullptr) {
     const int n_img = (int)J.imgs.size();
     const int64_t n_pairs = (int64_t)J.pair_q.size();
     // bucket tables for every train image
@@ -850,7 +926,6 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         }
     size_t tbytes = 0;
     std::vector<size_t> toff(n_img, 0), eoff(n_img, 0);
-    double sum_nt = 0, sum_nq = 0;
     for (int m : train_list) {
         toff[m] = tbytes;
         tbytes += (size_t)kTables * kOffStride * 4;
@@ -859,40 +934,16 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
         tbytes += ent_bytes(J.imgs[m].n, J.epi);
         tbytes = (tbytes + 255) & ~size_t(255);
     }
-    RETCHK(c->tables.ensure(tbytes));
-    std::vector<TableOut> touts(n_img, TableOut{nullptr, nullptr});
-    for (int m : train_list) {
-        touts[m] = TableOut{reinterpret_cast<uint32_t*>(c->tables.as<uint8_t>() + toff[m]),
-                            c->tables.as<uint8_t>() + eoff[m]};
-        J.imgs[m].off = touts[m].off;
-        J.imgs[m].ent = touts[m].ent;
-    }
-    // the bucket tables are built while the host plans the pairs
+    // batched: items ordered by train image, so the waves running together
+    // share one train image's tables in L2
     MatchPlan P;
-    {
-        Uploader up;
-        up.add(J.imgs);
-        up.add(touts);
-        up.add(train_list);
-        std::vector<const void*> d;
-        RETCHK(upload_meta(c, up, d, kMetaMatch));
-        P.dI = (const ImgDev*)d[0];
-        HIPCHK(launch_bucket(c->stream, J.epi, P.dI, (const TableOut*)d[1], (const int32_t*)d[2],
-                             (int)train_list.size()));
-    }
-    std::vector<PairDev> pd(n_pairs);
+    P.order.resize(n_pairs);
+    const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
+    double sum_nt = 0, sum_nq = 0;
     for (int64_t p = 0; p < n_pairs; ++p) {
-        pd[p].qi = J.pair_q[p];
-        pd[p].ti = J.pair_t[p];
-        pd[p].out = J.pair_out[p];
-        for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
         sum_nt += J.imgs[J.pair_t[p]].n;
         sum_nq += J.imgs[J.pair_q[p]].n;
     }
-    // batched: items ordered by train image, so the waves running together
-    // share one train image's tables in L2
-    P.order.resize(n_pairs);
-    const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
     if (batched) {
         // stable counting sort by (register-slot group, train image)
         std::vector<int64_t> start((size_t)3 * n_img + 1, 0);
@@ -909,7 +960,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
                                      n_pairs ? sum_nq / n_pairs : 0.0);
     std::vector<Shape> cands;
     auto hit = c->tuned.find(key);
-    const bool tune = hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
+    const bool tune = !sa && hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
     if (hit != c->tuned.end())
         cands.push_back(Shape{std::max(1, std::min({hit->second.qt, kMaxTile, kSelCap / c->cfg.k})), hit->second.bpc});
     else if (tune)
@@ -922,19 +973,86 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     std::vector<std::vector<PairTiles>> pts;
     std::vector<std::vector<int64_t>> firsts(qts.size());
     for (size_t i = 0; i < qts.size(); ++i) pts.push_back(pair_tiles(J, P.order, qts[i], &firsts[i]));
+    int64_t max_items = 1;
+    for (auto& f : firsts) max_items = std::max(max_items, f[n_pairs]);
+    P.items_cap = max_items;
 
-    Uploader up;
-    up.add(pd);
-    for (auto& t : pts) up.add(t);
+    std::vector<TableOut> touts(n_img, TableOut{nullptr, nullptr});
+    Uploader up1;  // image views, table outputs, train list (addresses patched below)
+    up1.add(J.imgs);
+    up1.add(touts);
+    up1.add(train_list);
+    std::vector<PairDev> pd(n_pairs);
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        pd[p].qi = J.pair_q[p];
+        pd[p].ti = J.pair_t[p];
+        pd[p].out = J.pair_out[p];
+        for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
+    }
+    Uploader up2;  // pairs, then the per-shape tile tables
+    up2.add(pd);
+    for (auto& t : pts) up2.add(t);
+    if (sa) {
+        // the whole call must fit the scratch before any device work starts
+        ScratchArea probe;
+        probe.base = sa->base;
+        probe.cap = sa->cap;
+        probe.used = sa->used;
+        const size_t pieces[] = {std::max<size_t>(tbytes, 1), std::max<size_t>(up1.host.size(), 1),
+                                 std::max<size_t>(up2.host.size(), 1), (size_t)max_items * sizeof(Item),
+                                 (size_t)kSegments * kCounterStride * 4, 64};
+        size_t need = 0;
+        for (size_t n : pieces) need = ((need + 255) & ~size_t(255)) + n;
+        for (size_t n : pieces)
+            if (!probe.take(n))
+                return fail(CASHASH_E_LIMIT, "the call needs %zu bytes of scratch, more than its %zu bytes", need,
+                            sa->cap);
+    }
+
+    uint8_t* tbase = nullptr;
+    if (sa) {
+        tbase = sa->take(std::max<size_t>(tbytes, 1));
+    } else {
+        RETCHK(c->tables.ensure(tbytes));
+        tbase = c->tables.as<uint8_t>();
+    }
+    for (int m : train_list) {
+        touts[m] = TableOut{reinterpret_cast<uint32_t*>(tbase + toff[m]), tbase + eoff[m]};
+        J.imgs[m].off = touts[m].off;
+        J.imgs[m].ent = touts[m].ent;
+    }
+    // the image views and table outputs now carry the table addresses
+    if (n_img > 0) {
+        std::memcpy(up1.host.data() + up1.offs[0], J.imgs.data(), J.imgs.size() * sizeof(ImgDev));
+        std::memcpy(up1.host.data() + up1.offs[1], touts.data(), touts.size() * sizeof(TableOut));
+    }
+    auto upload = [&](Uploader& up, std::vector<const void*>& d) {
+        return sa ? upload_scratch(c, *sa, up, d) : upload_meta(c, up, d, kMetaMatch);
+    };
     std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d, kMetaMatch));
+    RETCHK(upload(up1, d));
+    P.dI = (const ImgDev*)d[0];
+    HIPCHK(launch_bucket(c->stream, J.epi, P.dI, (const TableOut*)d[1], (const int32_t*)d[2],
+                         (int)train_list.size()));
+    RETCHK(upload(up2, d));
     P.dP = (const PairDev*)d[0];
     P.prm.k = c->cfg.k;
     P.prm.tau = c->cfg.max_hamming;
     P.prm.num2 = (int64_t)c->cfg.ratio_num * c->cfg.ratio_num;
     P.prm.den2 = (int64_t)c->cfg.ratio_den * c->cfg.ratio_den;
     P.prm.max_px = J.max_px;
-    unsigned long long* stats = c->dCount.as<unsigned long long>() + 8;
+    // work items (the most any candidate shape needs), counters, statistics
+    unsigned long long* stats = nullptr;
+    if (sa) {
+        P.items = reinterpret_cast<Item*>(sa->take((size_t)max_items * sizeof(Item)));
+        P.counter = reinterpret_cast<uint32_t*>(sa->take((size_t)kSegments * kCounterStride * 4));
+        stats = reinterpret_cast<unsigned long long*>(sa->take(64));
+    } else {
+        RETCHK(c->items.ensure((size_t)max_items * sizeof(Item)));
+        P.items = c->items.as<Item>();
+        P.counter = c->counters.as<uint32_t>();
+        stats = c->dCount.as<unsigned long long>() + 8;
+    }
 
     Shape best = cands[0];
     if (tune && cands.size() > 1) {
@@ -949,7 +1067,7 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
                 const Shape& sh = cands[ci];
                 const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), sh.qt) - qts.begin());
                 const int64_t n_it = firsts[qi][sample_pairs];
-                RETCHK(make_items(c, P, J, sh.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(),
+                RETCHK(make_items(c, P, sh.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(),
                                   firsts[qi][n_pairs]));
                 int64_t dummy_launches = 0;
                 HIPCHK(hipEventRecord(c->ev0, c->stream));
@@ -969,10 +1087,11 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J) {
     }
     const size_t qi = (size_t)(std::find(qts.begin(), qts.end(), best.qt) - qts.begin());
     const int64_t n_items = firsts[qi][n_pairs];
-    RETCHK(make_items(c, P, J, best.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(), n_items));
+    RETCHK(make_items(c, P, best.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(), n_items));
     HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
     HIPCHK(hipEventRecord(c->ev0, c->stream));
-    RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches, true));
+    RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches,
+                           sa == nullptr));
     HIPCHK(hipEventRecord(c->ev1, c->stream));
     c->last_shape_qt = best.qt;
     c->last_shape_bpc = best.bpc;
@@ -1411,7 +1530,8 @@ extern "C" int cashash_build_codes(cashash_ctx* c, const cashash_images* im, uin
 static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
                         const uint8_t* const* keys, const float* const* kp, int64_t n_pairs, const int32_t* pairs,
                         const double* F, double max_px, bool epi, int32_t* o_idx, int32_t* o_d1, int32_t* o_d2,
-                        cashash_stats* stats, const int64_t* out_offsets = nullptr) {
+                        cashash_stats* stats, const int64_t* out_offsets = nullptr,
+                        ScratchArea* sa = nullptr) {
     if (!c) return fail(CASHASH_E_INVAL, "null context");
     RETCHK(check_images(im));
     if (n_pairs < 0) return fail(CASHASH_E_INVAL, "negative n_pairs");
@@ -1469,7 +1589,7 @@ static int match_common(cashash_ctx* c, const cashash_images* im, const uint64_t
         J.o_d1 = o_d1;
         J.o_d2 = o_d2;
         c->last_ms = 0.0;
-        RETCHK(launch_match_job(c, J));
+        RETCHK(launch_match_job(c, J, sa));
         RETCHK(finish_match_job(c, J));
     } else {
         RETCHK(match_host(c, im, codes, keys, kp, J, o_idx, o_d1, o_d2, stats));
@@ -1493,6 +1613,20 @@ extern "C" int cashash_match_pairs(cashash_ctx* c, const cashash_images* im, con
                                    int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats) {
     return match_common(c, im, codes, keys, nullptr, n_pairs, pairs, nullptr, 0.0, false, match_idx, d1sq, d2sq,
                         stats);
+}
+
+extern "C" int cashash_match_pairs_noalloc(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
+                                           const uint8_t* const* keys, int64_t n_pairs, const int32_t* pairs,
+                                           int32_t* match_idx, int32_t* d1sq, int32_t* d2sq, cashash_stats* stats) {
+    if (!c) return fail(CASHASH_E_INVAL, "null context");
+    if (c->cfg.mem != CASHASH_MEM_DEVICE)
+        return fail(CASHASH_E_INVAL, "cashash_match_pairs_noalloc needs cfg.mem = CASHASH_MEM_DEVICE");
+    if (!c->scratch) return fail(CASHASH_E_DEVICE, "no scratch on device %d: %s", c->device, c->scratch_err.c_str());
+    ScratchArea sa;
+    sa.base = c->scratch;
+    sa.cap = (size_t)CASHASH_NOALLOC_SCRATCH_BYTES;
+    return match_common(c, im, codes, keys, nullptr, n_pairs, pairs, nullptr, 0.0, false, match_idx, d1sq, d2sq,
+                        stats, nullptr, &sa);
 }
 
 extern "C" int cashash_match_pairs_epipolar(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
