@@ -45,10 +45,10 @@ HBM_PEAK_GBS = 8000.0
 # SQ_INSTS_VALU.  Valid only for the matcher sources they were taken on
 # (sha256 over MATCHER_SOURCES, in order); null otherwise.
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_COUNTERS = {"sources_sha256": "7a66e258b8c437551b41b488a3763f60b0dbb83105040317a1412adab5bfcb8a",
+MEASURED_COUNTERS = {"sources_sha256": "9508b925ad6855f2e8390607111209762ae2bc27d197c6af719858f92286ce13",
                      "workload": "scenes_100x8000_exhaustive_4950pairs",
-                     "fetch_bytes": int(4298799.8 * 1024 * 2), "write_bytes": int(479093.1 * 1024),
-                     "valu_insts": 9139892569}
+                     "fetch_bytes": int(4368855.5 * 1024 * 2), "write_bytes": int(479178.5 * 1024),
+                     "valu_insts": 8436682177}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles (16 lanes per cycle), 2.4 GHz: 614.4 G instructions/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -456,7 +456,7 @@ def main():
         dt = time.perf_counter() - t
         if not quiet:
             log(f"{tag}: {n_steps} steps in {dt:.3f}s -> {n_pairs * n_steps / dt:.1f} pairs/s")
-        return dt, st_codes, st_match, kernel_ms, launches, dt / n_steps
+        return dt, st_codes, st_match, kernel_ms, launches, dt / max(n_steps, 1)
 
     m = binding.Matcher(*mats, mode="batched", mem="device")
     log("warmup (batched bf16x2)")

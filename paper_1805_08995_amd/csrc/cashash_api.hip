@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <map>
+#include <memory>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -28,6 +29,7 @@
 #include "cashash.h"
 #include "cashash_internal.h"
 #include "cashash_launch.h"
+#include "cashash_pool.h"
 #include "cashash_sched.h"
 
 using namespace cashash;
@@ -158,14 +160,19 @@ struct cashash_ctx {
     std::vector<int32_t> chunk_key;
     DevBuf chunk_dev;
     int chunk_ncol = 0, chunk_ntile = 0;
-    DevBuf stage, outbuf;     // host-memory mode: resident image slots; per-step outputs
+    DevBuf stage, outbuf[2];  // host-memory mode: resident image slots; per-step outputs (two steps in flight)
     HostPinned pin[2];        // host-memory mode upload staging
     hipEvent_t pin_ev[2] = {nullptr, nullptr};
     int pin_turn = 0;
-    HostPinned pin_out, pin_small;
+    HostPinned pin_out[2], pin_small;
     hipEvent_t slot_load_ev[3] = {nullptr, nullptr, nullptr};
     hipEvent_t slot_free_ev[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // autotuner timing
+    // per match job in flight (host-memory mode keeps two): kernel start and
+    // end, and the end of its output download
+    hipEvent_t job_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int job_turn = 0;
+    std::unique_ptr<WorkPool> pool;  // host threads of the bulk host copies
     double last_ms = 0.0;
     int64_t last_launches = 0;
     DevBuf items;             // matcher work items of the current job
@@ -207,7 +214,7 @@ static void quiesce(const cashash_ctx* c) {
 static std::vector<DevBuf*> dev_bufs(cashash_ctx* c) {
     return {&c->dR64, &c->dR32, &c->dFrag, &c->dBias, &c->dS, &c->dCount, &c->meta[0][0], &c->meta[0][1],
             &c->meta[1][0], &c->meta[1][1], &c->meta[2][0], &c->meta[2][1], &c->near, &c->tables, &c->stage,
-            &c->outbuf, &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err, &c->chunk_dev};
+            &c->outbuf[0], &c->outbuf[1], &c->items, &c->counters, &c->geo_sub, &c->geo_m1, &c->geo_pair, &c->geo_err, &c->chunk_dev};
 }
 
 static int validate_config(const cashash_config* c) {
@@ -302,13 +309,15 @@ static void destroy_ctx(cashash_ctx* c) {
     }
     for (DevBuf* b : dev_bufs(c)) b->release();
     for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
-                          &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out, &c->pin_small})
+                          &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out[0], &c->pin_out[1],
+                          &c->pin_small})
         h->release();
     for (hipEvent_t e : {c->ev0, c->ev1, c->meta_ev[0][0], c->meta_ev[0][1], c->meta_ev[1][0], c->meta_ev[1][1],
                          c->meta_ev[2][0], c->meta_ev[2][1], c->geo_ev[0], c->geo_ev[1], c->geo_ev[2], c->geo_ev[3],
                          c->geo_ev[4], c->pin_ev[0], c->pin_ev[1],
                          c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
-                         c->slot_free_ev[1], c->slot_free_ev[2], c->caller_ev})
+                         c->slot_free_ev[1], c->slot_free_ev[2], c->caller_ev, c->job_ev[0][0], c->job_ev[0][1],
+                         c->job_ev[0][2], c->job_ev[1][0], c->job_ev[1][1], c->job_ev[1][2]})
         if (e) hipEventDestroy(e);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -416,6 +425,16 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
         return bail(fail(CASHASH_E_DEVICE, "stream/event creation failed"));
     for (int i = 0; i < 5; ++i)
         if (hipEventCreate(&c->geo_ev[i]) != hipSuccess) return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
+    for (int j = 0; j < 2; ++j)
+        if (hipEventCreate(&c->job_ev[j][0]) != hipSuccess || hipEventCreate(&c->job_ev[j][1]) != hipSuccess ||
+            hipEventCreateWithFlags(&c->job_ev[j][2], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
+    {
+        // host copy threads: CASHASH_HOST_THREADS, else up to 8 of the host's
+        int nt = (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency()));
+        if (const char* e = std::getenv("CASHASH_HOST_THREADS")) nt = std::max(1, std::min(64, std::atoi(e)));
+        c->pool.reset(new WorkPool(nt));
+    }
     for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1],
                           &c->meta_ev[2][0], &c->meta_ev[2][1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
                           &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
@@ -641,6 +660,7 @@ struct MatchJob {
     int32_t* o_d1 = nullptr;
     int32_t* o_d2 = nullptr;
     int64_t bucket_entries = 0, union_size = 0, ranked = 0;
+    int turn = 0;                  // which of the two in-flight job slots (events, statistics) it uses
 };
 
 // ------------------------------------------------------------------ launch shape and autotuning
@@ -879,6 +899,12 @@ static int enqueue_matcher(cashash_ctx* c, const MatchPlan& P, MatchJob& J, Shap
     return CASHASH_OK;
 }
 
+// Pinned slot of job slot `turn`'s statistics (bucket entries, union,
+// ranked), after the first 256 bytes of pin_small.
+static unsigned long long* job_stats_host(cashash_ctx* c, int turn) {
+    return reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(c->pin_small.p) + 256 + 64 * turn);
+}
+
 // One caller-fixed device region that a match job carves its scratch out of
 // (bucket tables, uploaded tables, work items, counters, statistics) instead
 // of the context's growable buffers: the allocation-free entry point.
@@ -1089,13 +1115,15 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullp
     const int64_t n_items = firsts[qi][n_pairs];
     RETCHK(make_items(c, P, best.qt, (const PairTiles*)d[1 + qi], (int32_t)pts[qi].size(), n_items));
     HIPCHK(launch_fill_u64(c->stream, stats, 3, 0ull));
-    HIPCHK(hipEventRecord(c->ev0, c->stream));
+    J.turn = c->job_turn;
+    c->job_turn ^= 1;
+    HIPCHK(hipEventRecord(c->job_ev[J.turn][0], c->stream));
     RETCHK(enqueue_matcher(c, P, J, best, batched, firsts[qi], n_pairs, n_items, stats, &c->last_launches,
                            sa == nullptr));
-    HIPCHK(hipEventRecord(c->ev1, c->stream));
+    HIPCHK(hipEventRecord(c->job_ev[J.turn][1], c->stream));
     c->last_shape_qt = best.qt;
     c->last_shape_bpc = best.bpc;
-    HIPCHK(hipMemcpyAsync(c->pin_small.p, stats, 24, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(job_stats_host(c, J.turn), stats, 24, hipMemcpyDeviceToHost, c->stream));
     return CASHASH_OK;
 }
 
@@ -1126,11 +1154,17 @@ static void tune_cache_store(cashash_ctx* c, const std::string& key, Shape sh) {
     std::fclose(f);
 }
 
-static int finish_match_job(cashash_ctx* c, MatchJob& J) {
-    HIPCHK(hipStreamSynchronize(c->stream));
-    const unsigned long long* st = reinterpret_cast<const unsigned long long*>(c->pin_small.p);
+// Waits for job J (the whole stream, or only up to the job's done event,
+// recorded by the host-memory path after its output download) and takes its
+// statistics and kernel time.
+static int finish_match_job(cashash_ctx* c, MatchJob& J, bool whole_stream = true) {
+    if (whole_stream)
+        HIPCHK(hipStreamSynchronize(c->stream));
+    else
+        HIPCHK(hipEventSynchronize(c->job_ev[J.turn][2]));
+    const unsigned long long* st = job_stats_host(c, J.turn);
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    HIPCHK(hipEventElapsedTime(&ms, c->job_ev[J.turn][0], c->job_ev[J.turn][1]));
     c->last_ms += ms;
     J.bucket_entries += (int64_t)st[0];
     J.union_size += (int64_t)st[1];
@@ -1151,7 +1185,7 @@ static int h2d_staged(cashash_ctx* c, void* dst, const void* src, size_t bytes, 
         c->pin_turn ^= 1;
         HIPCHK(hipEventSynchronize(c->pin_ev[b]));
         const size_t n = std::min(chunk, bytes - off);
-        std::memcpy(c->pin[b].p, static_cast<const uint8_t*>(src) + off, n);
+        parallel_copy(*c->pool, c->pin[b].p, static_cast<const uint8_t*>(src) + off, n);
         HIPCHK(hipMemcpyAsync(static_cast<uint8_t*>(dst) + off, c->pin[b].p, n, hipMemcpyHostToDevice,
                               c->copy_stream));
         HIPCHK(hipEventRecord(c->pin_ev[b], c->copy_stream));
@@ -1282,30 +1316,32 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
         RETCHK(run_project(c, iv, ov, both ? n_tot : n_tot_set));
         size_t out_bytes = 0;
         for (int m = first[b]; m < first[b + 1]; ++m) out_bytes += (size_t)im->n_feat[m] * 22;
-        RETCHK(c->pin_out.ensure(out_bytes));
+        RETCHK(c->pin_out[0].ensure(out_bytes));
         size_t po = 0;
         for (int m = first[b]; m < first[b + 1]; ++m) {
             const size_t n = (size_t)im->n_feat[m];
             if (!n) continue;
             const SlotImage L = slot_layout((int)n, true, false);
             uint8_t* base = c->stage.as<uint8_t>() + place[m];
-            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out.p + po, base + L.codes, n * 16, hipMemcpyDeviceToHost,
+            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out[0].p + po, base + L.codes, n * 16, hipMemcpyDeviceToHost,
                                   c->stream));
-            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out.p + po + n * 16, base + L.keys, n * 6,
+            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out[0].p + po + n * 16, base + L.keys, n * 6,
                                   hipMemcpyDeviceToHost, c->stream));
             po += n * 22;
         }
         HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        po = 0;
-        for (int m = first[b]; m < first[b + 1]; ++m) {
+        std::vector<size_t> pos(first[b + 1] - first[b] + 1, 0);
+        for (int m = first[b]; m < first[b + 1]; ++m) pos[m - first[b] + 1] = pos[m - first[b]] + (size_t)im->n_feat[m] * 22;
+        const uint8_t* ho = static_cast<const uint8_t*>(c->pin_out[0].p);
+        c->pool->run(first[b + 1] - first[b], [&](int64_t i) {
+            const int m = first[b] + (int)i;
             const size_t n = (size_t)im->n_feat[m];
-            if (!n) continue;
-            std::memcpy(codes_out[m], (uint8_t*)c->pin_out.p + po, n * 16);
-            std::memcpy(keys_out[m], (uint8_t*)c->pin_out.p + po + n * 16, n * 6);
-            po += n * 22;
-            d2h += (int64_t)n * 22;
-        }
+            if (!n) return;
+            std::memcpy(codes_out[m], ho + pos[i], n * 16);
+            std::memcpy(keys_out[m], ho + pos[i] + n * 16, n * 6);
+        });
+        d2h += (int64_t)pos.back();
     }
     unsigned long long cnt = 0;
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1391,6 +1427,36 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         return -1;
     };
     c->last_ms = 0.0;
+    // a step whose kernels and download are queued; its outputs are copied
+    // into the caller's arrays (over the host threads) once the next step is
+    // queued behind it
+    struct Pending {
+        bool valid = false;
+        MatchJob job;
+        size_t step = 0;
+        int64_t nq = 0;
+    } pending;
+    auto drain = [&](Pending& pd) -> int {
+        pd.valid = false;
+        MatchJob& Jp = pd.job;
+        RETCHK(finish_match_job(c, Jp, false));
+        const int32_t* ho = reinterpret_cast<const int32_t*>(c->pin_out[Jp.turn].p);
+        const SchedStep& sp = S.steps[pd.step];
+        const int64_t nqp = pd.nq;
+        c->pool->run((int64_t)Jp.pair_q.size(), [&](int64_t i) {
+            const int64_t p = S.order[sp.pair_begin + i];
+            const int64_t n = im->n_feat[J.pair_q[p]];
+            if (!n) return;
+            std::memcpy(o_idx + J.pair_out[p], ho + Jp.pair_out[i], (size_t)n * 4);
+            std::memcpy(o_d1 + J.pair_out[p], ho + nqp + Jp.pair_out[i], (size_t)n * 4);
+            std::memcpy(o_d2 + J.pair_out[p], ho + 2 * nqp + Jp.pair_out[i], (size_t)n * 4);
+        });
+        d2h += nqp * 12;
+        J.bucket_entries += Jp.bucket_entries;
+        J.union_size += Jp.union_size;
+        J.ranked += Jp.ranked;
+        return CASHASH_OK;
+    };
     for (size_t st = 0; st < S.steps.size(); ++st) {
         const SchedStep& step = S.steps[st];
         for (int b : {step.bi, step.bk}) {
@@ -1427,15 +1493,19 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
             if (J.epi) Fs.insert(Fs.end(), J.F + 9 * p, J.F + 9 * p + 9);
         }
         Js.F = J.epi ? Fs.data() : nullptr;
-        RETCHK(c->outbuf.ensure((size_t)std::max<int64_t>(nq, 1) * 12));
-        Js.o_idx = c->outbuf.as<int32_t>();
+        const int turn = c->job_turn;  // the slot launch_match_job takes
+        RETCHK(c->outbuf[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
+        Js.o_idx = c->outbuf[turn].as<int32_t>();
         Js.o_d1 = Js.o_idx + nq;
         Js.o_d2 = Js.o_d1 + nq;
+        RETCHK(c->pin_out[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
         RETCHK(launch_match_job(c, Js));
         HIPCHK(hipEventRecord(c->slot_free_ev[si], c->stream));
         HIPCHK(hipEventRecord(c->slot_free_ev[sk], c->stream));
-        RETCHK(c->pin_out.ensure((size_t)std::max<int64_t>(nq, 1) * 12));
-        if (nq) HIPCHK(hipMemcpyAsync(c->pin_out.p, c->outbuf.p, (size_t)nq * 12, hipMemcpyDeviceToHost, c->stream));
+        if (nq)
+            HIPCHK(hipMemcpyAsync(c->pin_out[Js.turn].p, c->outbuf[Js.turn].p, (size_t)nq * 12,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->job_ev[Js.turn][2], c->stream));
         // prefetch the next step's new block while this one computes
         if (st + 1 < S.steps.size()) {
             const SchedStep& nx = S.steps[st + 1];
@@ -1447,21 +1517,15 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
                 break;  // one block ahead
             }
         }
-        RETCHK(finish_match_job(c, Js));
-        const int32_t* ho = reinterpret_cast<const int32_t*>(c->pin_out.p);
-        for (size_t i = 0; i < Js.pair_q.size(); ++i) {
-            const int64_t p = S.order[step.pair_begin + (int64_t)i];
-            const int64_t n = im->n_feat[J.pair_q[p]];
-            if (!n) continue;
-            std::memcpy(o_idx + J.pair_out[p], ho + Js.pair_out[i], (size_t)n * 4);
-            std::memcpy(o_d1 + J.pair_out[p], ho + nq + Js.pair_out[i], (size_t)n * 4);
-            std::memcpy(o_d2 + J.pair_out[p], ho + 2 * nq + Js.pair_out[i], (size_t)n * 4);
-        }
-        d2h += nq * 12;
-        J.bucket_entries += Js.bucket_entries;
-        J.union_size += Js.union_size;
-        J.ranked += Js.ranked;
+        // the previous step's results go to the caller while this one computes
+        if (pending.valid) RETCHK(drain(pending));
+        pending.valid = true;
+        pending.job = std::move(Js);
+        pending.job.F = nullptr;  // Fs ends with this step; the job's pair table holds F already
+        pending.step = st;
+        pending.nq = nq;
     }
+    if (pending.valid) RETCHK(drain(pending));
     if (stats) {
         stats->h2d_bytes = h2d;
         stats->d2h_bytes = d2h;

@@ -374,6 +374,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
     uint32_t* qtab = s_qtab[wv];
     const int part = lane & 3;
     uint64_t st_bucket = 0, st_ranked = 0;
+    uint64_t st_valid = 0;  // no Hamming filter: the union is the valid keys, counted per query (uniform)
     uint32_t st_union = 0;
     const double dd = prm.max_px * prm.max_px;
 
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             }
             wave_sync();
         }
-        uint32_t my_kk = 0, my_off = 0, sel_n = 0;
+        uint32_t sel_n = 0;
         const uint32_t jbits = tv.n > 1 ? 32u - (uint32_t)__clz(tv.n - 1) : 0u;
 
         // plain kernels: the next query's code (a wave-uniform address) is
@@ -519,10 +520,22 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             // vector registers (the kernel is short of scalar registers);
             // P6 bounds the loops and stays scalar.  The masked plain kernels
             // find runs by the chunk masks and need P1..P5 only when the runs
-            // exceed their register slots: they broadcast them there.
+            // exceed their register slots: there a copy of the query's view
+            // with them (runs_keyed) is made where it is read, so that no
+            // register holds them across the common path.
             auto bounds = [&]() {
                 qr.P1 = __shfl(v_P[0], qi); qr.P2 = __shfl(v_P[1], qi); qr.P3 = __shfl(v_P[2], qi);
                 qr.P4 = __shfl(v_P[3], qi); qr.P5 = __shfl(v_P[4], qi);
+            };
+            auto runs_keyed = [&]() -> QueryRuns {
+                if constexpr (kMask) {
+                    QueryRuns q = qr;
+                    q.P1 = __shfl(v_P[0], qi); q.P2 = __shfl(v_P[1], qi); q.P3 = __shfl(v_P[2], qi);
+                    q.P4 = __shfl(v_P[3], qi); q.P5 = __shfl(v_P[4], qi);
+                    return q;
+                } else {
+                    return qr;
+                }
             };
             if constexpr (!kMask && !EPI) bounds();
             qr.P6 = readlane(v_P[5], qi);
@@ -665,18 +678,20 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
 #pragma unroll
                     for (int u = 0; u < NS; ++u) {
                         if ((uint32_t)u < nch) {
-                            const bool keep = kr[u] != ~0u;
+                            // a valid key is below 129 << 16 (the empty key is ~0u); tested
+                            // this way, the compiler does not rebuild ~0u for the other lanes
+                            const bool keep = kr[u] < (129u << 16);
                             n_valid += (uint32_t)__popcll(__ballot(keep));
                             if (keep) atomicAdd(&hist[kr[u] >> 16], 1u);
                         }
                     }
                 } else {
-                    if constexpr (kMask) bounds();  // the only path that can leave in_regs false
+                    const QueryRuns qb = runs_keyed();  // the only path that can leave in_regs false
                     for (uint32_t base = 0; base < total; base += 256) {
                         uint32_t kv[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            kv[u] = key_at<EPI, kMask, FILT>(base + 64u * u + lane, tv, qr, prm.tau, dd, st_union);
+                            kv[u] = key_at<EPI, kMask, FILT>(base + 64u * u + lane, tv, qb, prm.tau, dd, st_union);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const bool keep = kv[u] != ~0u;
@@ -707,13 +722,13 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 nc0 = c.x;
                 nc1 = c.y;
             }
-            if constexpr (!FILT) st_union += lane == 0 ? n_valid : 0u;  // no filter: the union is the valid keys
+            if constexpr (!FILT) st_valid += n_valid;
             const uint32_t kk = n_valid < (uint32_t)prm.k ? n_valid : (uint32_t)prm.k;
             st_ranked += kk;
-            if (lane == qi) {
-                my_kk = kk;
-                my_off = sel_n;
-            }
+            // the query's kept count and first tile-list slot, for the ratio
+            // test; word 7 of its run table (its key bytes) is only read
+            // when the query starts
+            if (lane == 0) qtab[kQS * qi + 7] = kk | (sel_n << 16);
             if (kk == 0) continue;
             const bool in_list = n_valid <= (uint32_t)kListCap;
             const uint32_t span = in_list ? n_valid : total;
@@ -729,7 +744,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             for (uint32_t base = 0; base < span; base += 64) {                                        \
                 const uint32_t e = base + lane;                                                       \
                 const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)                          \
-                                             : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);            \
+                                             : key_at<EPI, kMask, FILT>(e, tv, runs_keyed(), prm.tau, dd, dummy);  \
                 c += (uint32_t)__popcll(__ballot(key >= (lo) && key < (hi)));                         \
             }                                                                                         \
         }                                                                                             \
@@ -791,7 +806,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         for (uint32_t base = 0; base < span; base += 64) {
                             const uint32_t e = base + lane;
                             const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                         : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);
+                                                         : key_at<EPI, kMask, FILT>(e, tv, runs_keyed(), prm.tau, dd, dummy);
                             const bool tie = key >= lo && key < hi;
                             const uint64_t mk = __ballot(tie);
                             const uint32_t slot = nt + mbcnt64(mk);
@@ -836,7 +851,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 for (uint32_t base = 0; base < span; base += 64) {
                     const uint32_t e = base + lane;
                     const uint32_t key = in_list ? (e < n_valid ? list[e] : ~0u)
-                                                 : key_at<EPI, kMask, FILT>(e, tv, qr, prm.tau, dd, dummy);
+                                                 : key_at<EPI, kMask, FILT>(e, tv, runs_keyed(), prm.tau, dd, dummy);
                     const bool keep = key <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
@@ -885,6 +900,8 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
 
         // ---- nearest, second nearest and ratio test, one lane per query
         if (lane < nq) {
+            const uint32_t kw = qtab[kQS * lane + 7];
+            const uint32_t my_kk = kw & 0xFFFFu, my_off = kw >> 16;
             uint64_t best = ~0ull;
             uint32_t sec = ~0u;
             for (uint32_t s = 0; s < my_kk; ++s) {
@@ -915,6 +932,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
     // statistics: bucket entries and ranked counts (uniform), union sizes (per lane)
     uint64_t u64 = st_union;
     for (int d = 32; d >= 1; d >>= 1) u64 += __shfl_xor(u64, d);
+    u64 += st_valid;
     if (lane == 0 && s_rare.stats) {
         atomicAdd(&s_rare.stats[0], (unsigned long long)st_bucket);
         atomicAdd(&s_rare.stats[1], (unsigned long long)u64);
