@@ -552,27 +552,33 @@ static int cached_chunks(cashash_ctx* c, const std::vector<ImgDev>& imgs) {
 
 // Column sums of imgs into c->dS; dchunks: device chunks (cached_chunks), or
 // nullptr to build and upload them with the image table.
+// dI: the image table already on the device (with dchunks), or nullptr.
 static int run_colsum(cashash_ctx* c, const std::vector<ImgDev>& imgs, const RowChunk* dchunks = nullptr,
-                      int n_chunks = 0) {
+                      int n_chunks = 0, const ImgDev* dI = nullptr) {
     std::vector<RowChunk> chunks;
     if (!dchunks) {
         row_chunks(imgs, 2048, chunks);
         n_chunks = (int)chunks.size();
     }
     if (n_chunks == 0) return CASHASH_OK;
-    Uploader up;
-    up.add(imgs);
-    if (!dchunks) up.add(chunks);
-    std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d, kMetaCodes));
-    HIPCHK(launch_colsum(c->stream, (const ImgDev*)d[0], dchunks ? dchunks : (const RowChunk*)d[1], n_chunks,
-                         c->dS.as<unsigned long long>()));
+    if (!dI || !dchunks) {
+        Uploader up;
+        up.add(imgs);
+        if (!dchunks) up.add(chunks);
+        std::vector<const void*> d;
+        RETCHK(upload_meta(c, up, d, kMetaCodes));
+        dI = (const ImgDev*)d[0];
+        if (!dchunks) dchunks = (const RowChunk*)d[1];
+    }
+    HIPCHK(launch_colsum(c->stream, dI, dchunks, n_chunks, c->dS.as<unsigned long long>()));
     return CASHASH_OK;
 }
 
 // Projection + binary64 fix-up of `imgs` into `outs`, given c->dBias and c->dS.
+// dI, dO: the image and output tables already on the device (with dtiles), or nullptr.
 static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vector<CodeOut> outs, double n_tot,
-                       const RowChunk* dtiles = nullptr, int n_tiles = 0) {
+                       const RowChunk* dtiles = nullptr, int n_tiles = 0, const ImgDev* dIp = nullptr,
+                       const CodeOut* dOp = nullptr) {
     std::vector<RowChunk> tiles;
     if (!dtiles) {
         row_chunks(imgs, 16, tiles);
@@ -592,15 +598,20 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     RETCHK(c->near.ensure(count_bytes + (size_t)n_seg * seg_cap * sizeof(NearEntry)));
     uint32_t* seg_count = c->near.as<uint32_t>();
     NearEntry* near = reinterpret_cast<NearEntry*>(c->near.as<uint8_t>() + count_bytes);
-    Uploader up;
-    up.add(imgs);
-    up.add(outs);
-    if (!dtiles) up.add(tiles);
-    std::vector<const void*> d;
-    RETCHK(upload_meta(c, up, d, kMetaCodes));
-    const ImgDev* dI = (const ImgDev*)d[0];
-    const CodeOut* dO = (const CodeOut*)d[1];
-    const RowChunk* dT = dtiles ? dtiles : (const RowChunk*)d[2];
+    const ImgDev* dI = dIp;
+    const CodeOut* dO = dOp;
+    const RowChunk* dT = dtiles;
+    if (!dI || !dO || !dtiles) {
+        Uploader up;
+        up.add(imgs);
+        up.add(outs);
+        if (!dtiles) up.add(tiles);
+        std::vector<const void*> d;
+        RETCHK(upload_meta(c, up, d, kMetaCodes));
+        dI = (const ImgDev*)d[0];
+        dO = (const CodeOut*)d[1];
+        if (!dtiles) dT = (const RowChunk*)d[2];
+    }
     const float coef = (float)c->cfg.margin_coef;
     if (mfma) {
         HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
@@ -636,15 +647,23 @@ static int build_codes_device(cashash_ctx* c, const cashash_images* im, uint64_t
     }
     RETCHK(cached_chunks(c, imgs));
     const RowChunk* dch = c->chunk_dev.as<RowChunk>();
+    // one upload of the image and output tables serves the sums and the projection
+    Uploader up;
+    up.add(imgs);
+    up.add(outs);
+    std::vector<const void*> d;
+    RETCHK(upload_meta(c, up, d, kMetaCodes));
     HIPCHK(launch_fill_u64(c->stream, c->dS.as<unsigned long long>(), kDim, 0ull));
     HIPCHK(launch_fill_u64(c->stream, c->dCount.as<unsigned long long>(), 8, 0ull));
-    RETCHK(run_colsum(c, imgs, dch, c->chunk_ncol));
+    RETCHK(run_colsum(c, imgs, dch, c->chunk_ncol, (const ImgDev*)d[0]));
     HIPCHK(launch_bias(c->stream, c->dR64.as<double>(), c->dS.as<unsigned long long>(), n_tot, c->dBias.as<float>()));
-    RETCHK(run_project(c, imgs, outs, n_tot, dch + c->chunk_ncol, c->chunk_ntile));
-    unsigned long long cnt = 0;
-    HIPCHK(hipMemcpyAsync(&cnt, c->dCount.p, 8, hipMemcpyDeviceToHost, c->stream));
+    RETCHK(run_project(c, imgs, outs, n_tot, dch + c->chunk_ncol, c->chunk_ntile, (const ImgDev*)d[0],
+                       (const CodeOut*)d[1]));
+    // the recompute count through pinned memory (offset 128 of pin_small)
+    unsigned long long* pc = reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(c->pin_small.p) + 128);
+    HIPCHK(hipMemcpyAsync(pc, c->dCount.p, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    *near_count = (int64_t)cnt;
+    *near_count = (int64_t)*pc;
     return CASHASH_OK;
 }
 
@@ -960,71 +979,105 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullp
         tbytes += ent_bytes(J.imgs[m].n, J.epi);
         tbytes = (tbytes + 255) & ~size_t(255);
     }
-    // batched: items ordered by train image, so the waves running together
-    // share one train image's tables in L2
+    // the pair plan (host work): visiting order, launch shapes, per-shape tile
+    // tables and the pair table.  Batched: items ordered by train image, so
+    // the waves running together share one train image's tables in L2.
     MatchPlan P;
     P.order.resize(n_pairs);
     const bool batched = c->cfg.mode == CASHASH_MODE_BATCHED_BF16X2;
-    double sum_nt = 0, sum_nq = 0;
-    for (int64_t p = 0; p < n_pairs; ++p) {
-        sum_nt += J.imgs[J.pair_t[p]].n;
-        sum_nq += J.imgs[J.pair_q[p]].n;
-    }
-    if (batched) {
-        // stable counting sort by (register-slot group, train image)
-        std::vector<int64_t> start((size_t)3 * n_img + 1, 0);
-        auto bucket = [&](int64_t p) { return (slots_for(J, p) / 2 - 2) * n_img + J.pair_t[p]; };
-        for (int64_t p = 0; p < n_pairs; ++p) start[(size_t)bucket(p) + 1]++;
-        for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
-        for (int64_t p = 0; p < n_pairs; ++p) P.order[(size_t)start[(size_t)bucket(p)]++] = p;
-    } else {
-        std::iota(P.order.begin(), P.order.end(), 0);
-    }
-    // launch shapes: cached, tuned now, or the default
-    tune_cache_load(c);
-    const std::string key = tune_key(batched, J.epi, c->cfg.k, n_pairs ? sum_nt / n_pairs : 0.0,
-                                     n_pairs ? sum_nq / n_pairs : 0.0);
+    std::string key;
     std::vector<Shape> cands;
-    auto hit = c->tuned.find(key);
-    const bool tune = !sa && hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
-    if (hit != c->tuned.end())
-        cands.push_back(Shape{std::max(1, std::min({hit->second.qt, kMaxTile, kSelCap / c->cfg.k})), hit->second.bpc});
-    else if (tune)
-        cands = shape_candidates(c->cfg.k, batched);
-    else
-        cands.push_back(default_shape(c->cfg.k, batched));
+    bool tune = false;
     std::vector<int> qts;
-    for (const Shape& sh : cands)
-        if (std::find(qts.begin(), qts.end(), sh.qt) == qts.end()) qts.push_back(sh.qt);
     std::vector<std::vector<PairTiles>> pts;
-    std::vector<std::vector<int64_t>> firsts(qts.size());
-    for (size_t i = 0; i < qts.size(); ++i) pts.push_back(pair_tiles(J, P.order, qts[i], &firsts[i]));
+    std::vector<std::vector<int64_t>> firsts;
     int64_t max_items = 1;
-    for (auto& f : firsts) max_items = std::max(max_items, f[n_pairs]);
-    P.items_cap = max_items;
-
-    std::vector<TableOut> touts(n_img, TableOut{nullptr, nullptr});
-    Uploader up1;  // image views, table outputs, train list (addresses patched below)
-    up1.add(J.imgs);
-    up1.add(touts);
-    up1.add(train_list);
-    std::vector<PairDev> pd(n_pairs);
-    for (int64_t p = 0; p < n_pairs; ++p) {
-        pd[p].qi = J.pair_q[p];
-        pd[p].ti = J.pair_t[p];
-        pd[p].out = J.pair_out[p];
-        for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
-    }
     Uploader up2;  // pairs, then the per-shape tile tables
-    up2.add(pd);
-    for (auto& t : pts) up2.add(t);
+    auto plan = [&]() {
+        double sum_nt = 0, sum_nq = 0;
+        for (int64_t p = 0; p < n_pairs; ++p) {
+            sum_nt += J.imgs[J.pair_t[p]].n;
+            sum_nq += J.imgs[J.pair_q[p]].n;
+        }
+        if (batched) {
+            // stable counting sort by (register-slot group, train image)
+            std::vector<int64_t> start((size_t)3 * n_img + 1, 0);
+            auto bucket = [&](int64_t p) { return (slots_for(J, p) / 2 - 2) * n_img + J.pair_t[p]; };
+            for (int64_t p = 0; p < n_pairs; ++p) start[(size_t)bucket(p) + 1]++;
+            for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+            for (int64_t p = 0; p < n_pairs; ++p) P.order[(size_t)start[(size_t)bucket(p)]++] = p;
+        } else {
+            std::iota(P.order.begin(), P.order.end(), 0);
+        }
+        // launch shapes: cached, tuned now, or the default
+        tune_cache_load(c);
+        key = tune_key(batched, J.epi, c->cfg.k, n_pairs ? sum_nt / n_pairs : 0.0, n_pairs ? sum_nq / n_pairs : 0.0);
+        auto hit = c->tuned.find(key);
+        tune = !sa && hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
+        if (hit != c->tuned.end())
+            cands.push_back(
+                Shape{std::max(1, std::min({hit->second.qt, kMaxTile, kSelCap / c->cfg.k})), hit->second.bpc});
+        else if (tune)
+            cands = shape_candidates(c->cfg.k, batched);
+        else
+            cands.push_back(default_shape(c->cfg.k, batched));
+        for (const Shape& sh : cands)
+            if (std::find(qts.begin(), qts.end(), sh.qt) == qts.end()) qts.push_back(sh.qt);
+        firsts.resize(qts.size());
+        for (size_t i = 0; i < qts.size(); ++i) pts.push_back(pair_tiles(J, P.order, qts[i], &firsts[i]));
+        for (auto& f : firsts) max_items = std::max(max_items, f[n_pairs]);
+        P.items_cap = max_items;
+        std::vector<PairDev> pd(n_pairs);
+        for (int64_t p = 0; p < n_pairs; ++p) {
+            pd[p].qi = J.pair_q[p];
+            pd[p].ti = J.pair_t[p];
+            pd[p].out = J.pair_out[p];
+            for (int i = 0; i < 9; ++i) pd[p].F[i] = J.epi ? J.F[9 * p + i] : 0.0;
+        }
+        up2.add(pd);
+        for (auto& t : pts) up2.add(t);
+    };
+    auto upload = [&](Uploader& up, std::vector<const void*>& d) {
+        return sa ? upload_scratch(c, *sa, up, d) : upload_meta(c, up, d, kMetaMatch);
+    };
+    // the bucket tables (device work): placed, their image and table views
+    // uploaded, the bucket kernel launched
+    std::vector<const void*> d;
+    auto tables = [&]() -> int {
+        uint8_t* tbase = nullptr;
+        if (sa) {
+            tbase = sa->take(std::max<size_t>(tbytes, 1));
+        } else {
+            RETCHK(c->tables.ensure(tbytes));
+            tbase = c->tables.as<uint8_t>();
+        }
+        std::vector<TableOut> touts(n_img, TableOut{nullptr, nullptr});
+        for (int m : train_list) {
+            touts[m] = TableOut{reinterpret_cast<uint32_t*>(tbase + toff[m]), tbase + eoff[m]};
+            J.imgs[m].off = touts[m].off;
+            J.imgs[m].ent = touts[m].ent;
+        }
+        Uploader up1;  // image views, table outputs, train list
+        up1.add(J.imgs);
+        up1.add(touts);
+        up1.add(train_list);
+        RETCHK(upload(up1, d));
+        P.dI = (const ImgDev*)d[0];
+        HIPCHK(launch_bucket(c->stream, J.epi, P.dI, (const TableOut*)d[1], (const int32_t*)d[2],
+                             (int)train_list.size()));
+        return CASHASH_OK;
+    };
     if (sa) {
         // the whole call must fit the scratch before any device work starts
+        plan();
+        const size_t up1_bytes = ((((size_t)n_img * sizeof(ImgDev) + 255) & ~size_t(255)) +
+                                  (((size_t)n_img * sizeof(TableOut) + 255) & ~size_t(255)) +
+                                  train_list.size() * sizeof(int32_t));
         ScratchArea probe;
         probe.base = sa->base;
         probe.cap = sa->cap;
         probe.used = sa->used;
-        const size_t pieces[] = {std::max<size_t>(tbytes, 1), std::max<size_t>(up1.host.size(), 1),
+        const size_t pieces[] = {std::max<size_t>(tbytes, 1), std::max<size_t>(up1_bytes, 1),
                                  std::max<size_t>(up2.host.size(), 1), (size_t)max_items * sizeof(Item),
                                  (size_t)kSegments * kCounterStride * 4, 64};
         size_t need = 0;
@@ -1033,33 +1086,12 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullp
             if (!probe.take(n))
                 return fail(CASHASH_E_LIMIT, "the call needs %zu bytes of scratch, more than its %zu bytes", need,
                             sa->cap);
-    }
-
-    uint8_t* tbase = nullptr;
-    if (sa) {
-        tbase = sa->take(std::max<size_t>(tbytes, 1));
+        RETCHK(tables());
     } else {
-        RETCHK(c->tables.ensure(tbytes));
-        tbase = c->tables.as<uint8_t>();
+        // the bucket tables are built while the host plans the pairs
+        RETCHK(tables());
+        plan();
     }
-    for (int m : train_list) {
-        touts[m] = TableOut{reinterpret_cast<uint32_t*>(tbase + toff[m]), tbase + eoff[m]};
-        J.imgs[m].off = touts[m].off;
-        J.imgs[m].ent = touts[m].ent;
-    }
-    // the image views and table outputs now carry the table addresses
-    if (n_img > 0) {
-        std::memcpy(up1.host.data() + up1.offs[0], J.imgs.data(), J.imgs.size() * sizeof(ImgDev));
-        std::memcpy(up1.host.data() + up1.offs[1], touts.data(), touts.size() * sizeof(TableOut));
-    }
-    auto upload = [&](Uploader& up, std::vector<const void*>& d) {
-        return sa ? upload_scratch(c, *sa, up, d) : upload_meta(c, up, d, kMetaMatch);
-    };
-    std::vector<const void*> d;
-    RETCHK(upload(up1, d));
-    P.dI = (const ImgDev*)d[0];
-    HIPCHK(launch_bucket(c->stream, J.epi, P.dI, (const TableOut*)d[1], (const int32_t*)d[2],
-                         (int)train_list.size()));
     RETCHK(upload(up2, d));
     P.dP = (const PairDev*)d[0];
     P.prm.k = c->cfg.k;
