@@ -594,10 +594,15 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     const int grid = mfma ? std::max(1, std::min((groups + 3) / 4, c->n_cu * 8)) : (int)(((int64_t)nt * 16 + 255) / 256);
     const uint32_t n_seg = (uint32_t)grid * 4;
     const uint32_t seg_cap = mfma ? (uint32_t)((groups + n_seg - 1) / n_seg) * kProjTB * 16 : 64;
+    const uint64_t n_cap = (uint64_t)n_seg * seg_cap;
+    if (n_cap >= ((uint64_t)1 << 32)) return fail(CASHASH_E_LIMIT, "more than 2^32 near-list places");
+    // segment counts, near list, recompute work area
     const size_t count_bytes = al256((size_t)n_seg * 4);
-    RETCHK(c->near.ensure(count_bytes + (size_t)n_seg * seg_cap * sizeof(NearEntry)));
+    const size_t list_bytes = al256((size_t)n_cap * sizeof(NearEntry));
+    RETCHK(c->near.ensure(count_bytes + list_bytes + near_work_bytes(n_cap)));
     uint32_t* seg_count = c->near.as<uint32_t>();
     NearEntry* near = reinterpret_cast<NearEntry*>(c->near.as<uint8_t>() + count_bytes);
+    void* work = c->near.as<uint8_t>() + count_bytes + list_bytes;
     const ImgDev* dI = dIp;
     const CodeOut* dO = dOp;
     const RowChunk* dT = dtiles;
@@ -615,14 +620,16 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     const float coef = (float)c->cfg.margin_coef;
     if (mfma) {
         HIPCHK(launch_proj_mfma(c->stream, grid, dI, dO, dT, nt, c->dFrag.as<uint4>(), c->dBias.as<float>(), coef,
-                                near, seg_count, seg_cap));
+                                near, seg_count, seg_cap, work));
     } else {
         HIPCHK(launch_proj_fp32(c->stream, dI, dO, dT, nt, c->dR32.as<float>(), c->dBias.as<float>(), coef, near,
-                                seg_count));
+                                seg_count, work));
     }
+    // the recompute: as many wavefronts as the near list has segments, at
+    // most 16 per compute unit
     const int fix_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_seg + 3) / 4, (int64_t)c->n_cu * 4));
     HIPCHK(launch_fixup(c->stream, fix_grid, dI, dO, near, seg_count, seg_cap, n_seg, c->dR64.as<double>(),
-                        c->dS.as<unsigned long long>(), n_tot, c->dCount.as<unsigned long long>()));
+                        c->dS.as<unsigned long long>(), n_tot, work, c->dCount.as<unsigned long long>()));
     return CASHASH_OK;
 }
 

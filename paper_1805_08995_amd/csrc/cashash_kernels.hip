@@ -8,11 +8,17 @@
 // recomputed in binary64 exactly as the reference definition does it.
 // Bucket tables: per train image and table, a stable counting sort of the
 // 8-bit keys whose entries carry code, keys and index (Step 1 lookup runs).
+#include <algorithm>
+
 #include "cashash_device.h"
 
 namespace cashash {
 
 // ------------------------------------------------------------------ utilities
+
+// Control words of the binary64 recompute (jobs per row, overflow flag),
+// cleared by block 0 of the projection kernel (256 threads) before use.
+constexpr int kNearCtlWords = 256;
 
 __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -150,7 +156,9 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
                                                         const uint4* __restrict__ frag,
                                                         const float* __restrict__ bias, float margin_coef,
                                                         NearEntry* __restrict__ near,
-                                                        uint32_t* __restrict__ seg_count, uint32_t seg_cap) {
+                                                        uint32_t* __restrict__ seg_count, uint32_t seg_cap,
+                                                        uint32_t* __restrict__ near_ctl) {
+    if (blockIdx.x == 0) near_ctl[threadIdx.x] = 0u;  // the recompute's control words (kNearCtlWords)
     constexpr int TB = kProjTB;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
@@ -245,7 +253,9 @@ __global__ __launch_bounds__(256) void proj_fp32_kernel(const ImgDev* __restrict
                                                         const float* __restrict__ R32,
                                                         const float* __restrict__ bias, float margin_coef,
                                                         NearEntry* __restrict__ near,
-                                                        uint32_t* __restrict__ seg_count) {
+                                                        uint32_t* __restrict__ seg_count,
+                                                        uint32_t* __restrict__ near_ctl) {
+    if (blockIdx.x == 0) near_ctl[threadIdx.x] = 0u;  // the recompute's control words (kNearCtlWords)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int tile = min(t >> 4, n_tiles - 1), n = t & 15;
     const RowChunk tc = tiles[tile];
@@ -292,34 +302,196 @@ __global__ __launch_bounds__(256) void proj_fp32_kernel(const ImgDev* __restrict
     if ((t & 63) == 0) seg_count[wave] = cnt;
 }
 
-// Binary64 recompute of near-margin projections: the same fused
-// multiply-add chain over components 0..127 of r_j . (N x - S) that defines
-// the codes; N x_i - S_i is an exact integer in binary64.  One wavefront per
-// segment of the near list (grid-stride).  The (descriptor, row) recomputes
-// of up to 64 listed descriptors are spread over the lanes 64 at a time,
-// whichever descriptor they belong to, so a descriptor with many flagged
-// rows does not hold its lane for all of them; their bits are OR-ed into
-// per-descriptor words in LDS, and the lane that read a descriptor's entry
-// then ORs them into its code and keys (the only writer of that code).  The
-// recompute count is reduced over the block and added with one atomic.
-__global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ imgs,
-                                                    const CodeOut* __restrict__ outs,
-                                                    const NearEntry* __restrict__ near,
-                                                    const uint32_t* __restrict__ seg_count, uint32_t seg_cap,
-                                                    uint32_t n_seg, const double* __restrict__ R,
-                                                    const unsigned long long* __restrict__ S, double n_tot,
-                                                    unsigned long long* __restrict__ counter) {
-    __shared__ double s_S[kDim];
-    __shared__ uint32_t s_pre[4][64];                 // per wave: inclusive prefix of recomputes per entry
-    __shared__ unsigned long long s_bits[4][64][3];   // per wave and entry: recomputed bits
-    __shared__ uint32_t s_cnt[4];
-    for (int i = threadIdx.x; i < kDim; i += blockDim.x) s_S[i] = (double)S[i];
+// ------------------------------------------------------------------ binary64 recompute
+// Near-margin projections are recomputed with the same fused multiply-add
+// chain over components 0..127 of r_j . (N x - S) that defines the codes
+// (N x_i - S_i is an exact integer in binary64).  A recompute is a job
+// (near-list entry, row j).  The jobs are grouped by row first, so that the
+// wavefront evaluating 64 of them reads one row of R, with wave-uniform
+// (scalar) loads, and only the descriptors differ per lane:
+//   near_sort  : per block of kSortSegs near-list segments, count the jobs
+//                of each row, reserve their places in the row's region of
+//                the job list (one atomic per block and row), place them;
+//                clear the result bits of the entries;
+//   near_eval  : one wavefront per 64 jobs of one row; a positive value ORs
+//                the row's bit into the entry's result bits;
+//   near_apply : the result bits ORed into each entry's code and keys (one
+//                thread per entry, the only writer of that descriptor).
+// A row region holds cap_r jobs.  If some row has more, near_eval takes its
+// spread form instead: the jobs of each segment are spread over the lanes
+// as they come (any row per lane, rows read with vector loads); the results
+// are the same.  Block sizes measured on 800k descriptors (190k jobs):
+// 32 segments per near_sort block (fewer blocks: longer passes; more: more
+// row reservations), 8 per near_apply block (about one entry per thread).
+constexpr int kSortSegs = 32;
+constexpr int kApplySegs = 8;
+
+struct NearJob {
+    uint32_t entry;       // near-list index sg * seg_cap + i
+    uint32_t pad;
+    const uint8_t* x;     // the descriptor
+};
+
+constexpr int kNearOverflow = kRows;  // control word: some row has more jobs than its region
+
+// The near-list entries of a block's SEGS segments from s0 on, flattened:
+// s_pre[j] is the number of entries in segments s0 .. s0 + j - 1.
+template <int SEGS>
+__device__ __forceinline__ uint32_t near_entry_of(const uint32_t* s_pre, uint32_t i, uint32_t s0, uint32_t seg_cap) {
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t step = SEGS / 2; step >= 1; step >>= 1)
+        if (s_pre[j + step] <= i) j += step;
+    return (s0 + j) * seg_cap + (i - s_pre[j]);
+}
+
+template <int SEGS>
+__device__ __forceinline__ void near_block_prefix(uint32_t* s_pre, const uint32_t* seg_count, uint32_t s0,
+                                                  uint32_t n_seg) {
+    static_assert(SEGS >= 2 && SEGS <= 64 && (SEGS & (SEGS - 1)) == 0, "SEGS: a power of two up to 64");
+    if (threadIdx.x < 64) {
+        const uint32_t t = threadIdx.x;
+        const uint32_t c = (t < SEGS && s0 + t < n_seg) ? seg_count[s0 + t] : 0u;
+        const uint32_t incl = wave_incl_scan(c, (int)t);
+        if (t < SEGS) s_pre[t + 1] = incl;
+        if (t == 0) s_pre[0] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void near_sort_kernel(const ImgDev* __restrict__ imgs,
+                                                        const NearEntry* __restrict__ near,
+                                                        const uint32_t* __restrict__ seg_count, uint32_t seg_cap,
+                                                        uint32_t n_seg, unsigned long long* __restrict__ res,
+                                                        uint32_t* __restrict__ ctl, NearJob* __restrict__ jobs,
+                                                        uint32_t cap_r, unsigned long long* __restrict__ counter) {
+    __shared__ uint32_t s_pre[kSortSegs + 1];
+    __shared__ uint32_t s_hist[kRows];
+    __shared__ uint32_t s_tot[4];
+    const uint32_t s0 = blockIdx.x * kSortSegs;
+    near_block_prefix<kSortSegs>(s_pre, seg_count, s0, n_seg);
+    for (int r = threadIdx.x; r < kRows; r += blockDim.x) s_hist[r] = 0;
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-    uint32_t cnt = 0;
-    for (uint32_t sg = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); sg < n_seg; sg += n_waves) {
+    const uint32_t n_ent = s_pre[kSortSegs];
+    // pass 1: jobs per row; result bits cleared
+    uint32_t tot = 0;
+    for (uint32_t i = threadIdx.x; i < n_ent; i += blockDim.x) {
+        const uint32_t e = near_entry_of<kSortSegs>(s_pre, i, s0, seg_cap);
+        const NearEntry ne = near[e];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+            res[3 * (size_t)e + w] = 0ull;
+            for (uint64_t m = ne.mask[w]; m; m &= m - 1) {
+                atomicAdd(&s_hist[64 * w + __ffsll((unsigned long long)m) - 1], 1u);
+                ++tot;
+            }
+        }
+    }
+    tot += __shfl_xor(tot, 1);
+    tot += __shfl_xor(tot, 2);
+    tot += __shfl_xor(tot, 4);
+    tot += __shfl_xor(tot, 8);
+    tot += __shfl_xor(tot, 16);
+    tot += __shfl_xor(tot, 32);
+    if ((threadIdx.x & 63) == 0) s_tot[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    // reserve each row's places (s_hist becomes the row's next free place)
+    for (int r = threadIdx.x; r < kRows; r += blockDim.x) {
+        const uint32_t h = s_hist[r];
+        uint32_t b = 0;
+        if (h) {
+            b = atomicAdd(&ctl[r], h);
+            if (b + h > cap_r) ctl[kNearOverflow] = 1u;
+        }
+        s_hist[r] = b;
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t t = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+        if (t) atomicAdd(counter, (unsigned long long)t);
+    }
+    __syncthreads();
+    // pass 2: place the jobs
+    for (uint32_t i = threadIdx.x; i < n_ent; i += blockDim.x) {
+        const uint32_t e = near_entry_of<kSortSegs>(s_pre, i, s0, seg_cap);
+        const NearEntry ne = near[e];
+        const uint8_t* x = imgs[ne.img].desc + (int64_t)ne.row * kDim;
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+            for (uint64_t m = ne.mask[w]; m; m &= m - 1) {
+                const int r = 64 * w + __ffsll((unsigned long long)m) - 1;
+                const uint32_t pos = atomicAdd(&s_hist[r], 1u);
+                if (pos < cap_r) jobs[(size_t)r * cap_r + pos] = NearJob{e, 0u, x};
+            }
+    }
+}
+
+// The binary64 chain of one descriptor x (per lane) against row rp: c_i =
+// N x_i - S_i exactly, then p = fma(r_i, c_i, p) for i = 0 .. 127.
+__device__ __forceinline__ double near_chain_q(double p, uint4 xv, const double rv[16], const double* s_S, int q,
+                                               double n_tot) {
+    const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int ci = 16 * q + 4 * a + bb;
+            const double c = n_tot * (double)((xw[a] >> (8 * bb)) & 0xFFu) - s_S[ci];
+            p = fma(rv[4 * a + bb], c, p);
+        }
+    return p;
+}
+
+// Row rp the same for the whole wavefront (scalar loads).  The descriptor is
+// loaded whole; the scheduling barriers keep the conversions of each group
+// of 16 components next to their multiply-adds (hoisting all 128 would need
+// 256 registers).
+__device__ __forceinline__ double near_chain_uniform(const uint8_t* x, const double* __restrict__ rp,
+                                                     const double* s_S, double n_tot) {
+    const uint4* xp = reinterpret_cast<const uint4*>(x);
+    uint4 xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = gload(xp + q);
+    double p = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double rv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rv[i] = rp[16 * q + i];
+        p = near_chain_q(p, xv[q], rv, s_S, q, n_tot);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return p;
+}
+
+// Row rp per lane (vector loads, 16 components at a time).
+__device__ __forceinline__ double near_chain_lane(const uint8_t* x, const double* rp, const double* s_S,
+                                                  double n_tot) {
+    const uint4* xp = reinterpret_cast<const uint4*>(x);
+    const double2* rr = reinterpret_cast<const double2*>(rp);
+    double p = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+        double rv[16];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double2 v = rr[8 * q + i];
+            rv[2 * i] = v.x;
+            rv[2 * i + 1] = v.y;
+        }
+        p = near_chain_q(p, gload(xp + q), rv, s_S, q, n_tot);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return p;
+}
+
+// The spread form of the recompute, used when some row has more jobs than
+// its region holds: per segment, the (entry, row) jobs of up to 64 entries
+// are spread over the lanes 64 at a time, whichever entry they belong to.
+__device__ __forceinline__ void near_eval_spread(const ImgDev* __restrict__ imgs, const NearEntry* __restrict__ near,
+                                                 const uint32_t* __restrict__ seg_count, uint32_t seg_cap,
+                                                 uint32_t n_seg, const double* __restrict__ R, const double* s_S,
+                                                 double n_tot, unsigned long long* __restrict__ res, uint32_t* s_fb,
+                                                 int lane, uint32_t wave, uint32_t n_waves) {
+    for (uint32_t sg = wave; sg < n_seg; sg += n_waves) {
         const uint32_t ns = uniform(seg_count[sg]);
         for (uint32_t base = 0; base < ns; base += 64) {
             const uint32_t i = base + (uint32_t)lane;
@@ -329,10 +501,8 @@ __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ i
             const uint32_t pc = has ? (uint32_t)(__popcll(e.mask[0]) + __popcll(e.mask[1]) + __popcll(e.mask[2])) : 0u;
             const uint32_t incl = wave_incl_scan(pc, lane);
             const uint32_t total = uniform(__shfl(incl, 63));
-            s_pre[wv][lane] = incl;
-            s_bits[wv][lane][0] = s_bits[wv][lane][1] = s_bits[wv][lane][2] = 0ull;
+            s_fb[lane] = incl;
             wave_sync();
-            cnt += total;
             for (uint32_t j0 = 0; j0 < total; j0 += 64) {
                 const uint32_t j = j0 + (uint32_t)lane;
                 const bool act = j < total;
@@ -340,9 +510,9 @@ __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ i
                 uint32_t L = 0;
 #pragma unroll
                 for (uint32_t step = 32; step >= 1; step >>= 1)
-                    if (s_pre[wv][L + step - 1] <= j) L += step;
+                    if (s_fb[L + step - 1] <= j) L += step;
                 L = act ? L : 0u;
-                const uint32_t start = L ? s_pre[wv][L - 1] : 0u;
+                const uint32_t start = L ? s_fb[L - 1] : 0u;
                 uint32_t kth = act ? j - start : 0u;
                 const uint64_t m0 = __shfl(e.mask[0], (int)L), m1 = __shfl(e.mask[1], (int)L),
                                m2 = __shfl(e.mask[2], (int)L);
@@ -365,50 +535,103 @@ __global__ __launch_bounds__(256) void fixup_kernel(const ImgDev* __restrict__ i
                 const int bitpos = w ? __ffsll((unsigned long long)w) - 1 : 0;
                 if (act) {
                     const int r = 64 * word + bitpos;
-                    const uint4* xp = reinterpret_cast<const uint4*>(imgs[img].desc + (int64_t)row * kDim);
-                    const double2* rr = reinterpret_cast<const double2*>(R + r * kDim);
-                    double p = 0.0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const uint4 xv = gload(xp + q);
-                        const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const double2 r01 = rr[8 * q + 2 * a], r23 = rr[8 * q + 2 * a + 1];
-                            const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
-#pragma unroll
-                            for (int bb = 0; bb < 4; ++bb) {
-                                const int ci = 16 * q + 4 * a + bb;
-                                const double c = n_tot * (double)((xw[a] >> (8 * bb)) & 0xFFu) - s_S[ci];
-                                p = fma(rv[bb], c, p);
-                            }
-                        }
-                    }
-                    if (p > 0.0) atomicOr(&s_bits[wv][L][word], 1ull << bitpos);
+                    const double p =
+                        near_chain_lane(imgs[img].desc + (int64_t)row * kDim, R + (size_t)r * kDim, s_S, n_tot);
+                    if (p > 0.0)
+                        atomicOr(&res[3 * ((size_t)sg * seg_cap + base + L) + word], 1ull << bitpos);
                 }
             }
-            wave_sync();
-            if (has && pc) {
-                const CodeOut o = outs[e.img];
-                const int64_t row = e.row;
-                const uint64_t b0 = s_bits[wv][lane][0], b1 = s_bits[wv][lane][1], b2 = s_bits[wv][lane][2];
-                if (b0 | b1) {
-                    o.codes[2 * row] |= b0;
-                    o.codes[2 * row + 1] |= b1;
-                }
-                if (b2) {
-                    uint8_t* kb = o.keys + 6 * row;
-                    for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((b2 >> (8 * tb)) & 0xFFu));
-                }
-            }
-            wave_sync();  // s_pre and s_bits are rewritten by the next batch
+            wave_sync();  // s_fb is rewritten by the next batch
         }
     }
-    if (lane == 0) s_cnt[wv] = cnt;
+}
+
+__global__ __launch_bounds__(256) void near_eval_kernel(const NearJob* __restrict__ jobs, uint32_t cap_r,
+                                                        const uint32_t* __restrict__ ctl,
+                                                        const double* __restrict__ R,
+                                                        const unsigned long long* __restrict__ S, double n_tot,
+                                                        unsigned long long* __restrict__ res,
+                                                        const ImgDev* __restrict__ imgs,
+                                                        const NearEntry* __restrict__ near,
+                                                        const uint32_t* __restrict__ seg_count, uint32_t seg_cap,
+                                                        uint32_t n_seg) {
+    __shared__ double s_S[kDim];
+    __shared__ uint32_t s_pre[kRows + 1];  // first 64-job chunk of each row
+    __shared__ uint32_t s_n[kRows];        // jobs of each row
+    __shared__ uint32_t s_fb[4][64];       // spread form: per wave, inclusive prefix of jobs per entry
+    for (int i = threadIdx.x; i < kDim; i += blockDim.x) s_S[i] = (double)S[i];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t wave = uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const bool overflow = uniform(ctl[kNearOverflow]) != 0u;
+    if (!overflow && threadIdx.x < 64) {
+        // lane l: rows 3l .. 3l + 2
+        uint32_t c[3], sum = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int r = 3 * lane + a;
+            const uint32_t n = r < kRows ? min(ctl[r], cap_r) : 0u;
+            if (r < kRows) s_n[r] = n;
+            c[a] = (n + 63) >> 6;
+            sum += c[a];
+        }
+        const uint32_t incl = wave_incl_scan(sum, lane);
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int r = 3 * lane + a;
+            if (r < kRows) s_pre[r] = run;
+            run += c[a];
+        }
+        if (lane == 63) s_pre[kRows] = incl;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-        if (tot) atomicAdd(counter, (unsigned long long)tot);
+    if (overflow) {
+        near_eval_spread(imgs, near, seg_count, seg_cap, n_seg, R, s_S, n_tot, res, s_fb[wv], lane, wave, n_waves);
+        return;
+    }
+    const uint32_t n_chunks = uniform(s_pre[kRows]);
+    for (uint32_t ch = wave; ch < n_chunks; ch += n_waves) {
+        // the row: the last one whose first chunk is <= ch
+        uint32_t r = 0;
+#pragma unroll
+        for (uint32_t step = 128; step >= 1; step >>= 1)
+            if (r + step < kRows && s_pre[r + step] <= ch) r += step;
+        r = uniform(r);
+        const uint32_t j = 64 * (ch - s_pre[r]) + (uint32_t)lane;
+        if (j < s_n[r]) {
+            const NearJob jb = jobs[(size_t)r * cap_r + j];
+            const double p = near_chain_uniform(jb.x, R + (size_t)r * kDim, s_S, n_tot);
+            if (p > 0.0) atomicOr(&res[3 * (size_t)jb.entry + (r >> 6)], 1ull << (r & 63));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void near_apply_kernel(const CodeOut* __restrict__ outs,
+                                                         const NearEntry* __restrict__ near,
+                                                         const uint32_t* __restrict__ seg_count, uint32_t seg_cap,
+                                                         uint32_t n_seg, const unsigned long long* __restrict__ res) {
+    __shared__ uint32_t s_pre[kApplySegs + 1];
+    const uint32_t s0 = blockIdx.x * kApplySegs;
+    near_block_prefix<kApplySegs>(s_pre, seg_count, s0, n_seg);
+    __syncthreads();
+    const uint32_t n_ent = s_pre[kApplySegs];
+    for (uint32_t i = threadIdx.x; i < n_ent; i += blockDim.x) {
+        const uint32_t e = near_entry_of<kApplySegs>(s_pre, i, s0, seg_cap);
+        const uint64_t b0 = res[3 * (size_t)e], b1 = res[3 * (size_t)e + 1], b2 = res[3 * (size_t)e + 2];
+        if (!(b0 | b1 | b2)) continue;
+        const NearEntry ne = near[e];
+        const CodeOut o = outs[ne.img];
+        const int64_t row = ne.row;
+        if (b0 | b1) {
+            o.codes[2 * row] |= b0;
+            o.codes[2 * row + 1] |= b1;
+        }
+        if (b2) {
+            uint8_t* kb = o.keys + 6 * row;
+            for (int tb = 0; tb < kTables; ++tb) kb[tb] = (uint8_t)(kb[tb] | ((b2 >> (8 * tb)) & 0xFFu));
+        }
     }
 }
 
@@ -535,29 +758,51 @@ hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long*
 
 hipError_t launch_proj_mfma(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
                             int n_tiles, const uint4* frag, const float* bias, float margin, NearEntry* near,
-                            uint32_t* seg_count, uint32_t seg_cap) {
+                            uint32_t* seg_count, uint32_t seg_cap, void* near_work) {
     if (n_tiles <= 0) return hipSuccess;
     CH_LAUNCH(proj_mfma_kernel, dim3(grid), dim3(256), 0, s, imgs, outs, tiles, n_tiles, frag, bias, margin, near,
-              seg_count, seg_cap);
+              seg_count, seg_cap, static_cast<uint32_t*>(near_work));
     return hipSuccess;
 }
 
 hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
                             int n_tiles, const float* R32, const float* bias, float margin, NearEntry* near,
-                            uint32_t* seg_count) {
+                            uint32_t* seg_count, void* near_work) {
     if (n_tiles <= 0) return hipSuccess;
     const int64_t threads = (int64_t)n_tiles * 16;
     CH_LAUNCH(proj_fp32_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, imgs, outs, tiles, n_tiles,
-              R32, bias, margin, near, seg_count);
+              R32, bias, margin, near, seg_count, static_cast<uint32_t*>(near_work));
     return hipSuccess;
 }
 
-hipError_t launch_fixup(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+uint32_t near_row_cap(uint64_t n_cap) {
+    const uint64_t c = std::max<uint64_t>(64, (n_cap + kRows - 1) / kRows);
+    return (uint32_t)((c + 63) & ~uint64_t(63));
+}
+
+// Work area: control words, result bits (3 words per near-list place), jobs.
+size_t near_work_bytes(uint64_t n_cap) {
+    const size_t res = ((size_t)n_cap * 24 + 255) & ~size_t(255);
+    return (size_t)kNearCtlWords * 4 + res + (size_t)kRows * near_row_cap(n_cap) * sizeof(NearJob);
+}
+
+hipError_t launch_fixup(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
                         const uint32_t* seg_count, uint32_t seg_cap, uint32_t n_seg, const double* R,
-                        const unsigned long long* S, double n_tot, unsigned long long* counter) {
+                        const unsigned long long* S, double n_tot, void* work, unsigned long long* counter) {
     if (n_seg == 0) return hipSuccess;
-    CH_LAUNCH(fixup_kernel, dim3(grid), dim3(256), 0, s, imgs, outs, near, seg_count, seg_cap, n_seg, R, S, n_tot,
-              counter);
+    const uint64_t n_cap = (uint64_t)n_seg * seg_cap;
+    const uint32_t cap_r = near_row_cap(n_cap);
+    uint32_t* ctl = static_cast<uint32_t*>(work);
+    unsigned long long* res = reinterpret_cast<unsigned long long*>(ctl + kNearCtlWords);
+    NearJob* jobs = reinterpret_cast<NearJob*>(reinterpret_cast<uint8_t*>(res) +
+                                               (((size_t)n_cap * 24 + 255) & ~size_t(255)));
+    const unsigned blocks = (n_seg + kSortSegs - 1) / kSortSegs;
+    const unsigned ablocks = (n_seg + kApplySegs - 1) / kApplySegs;
+    CH_LAUNCH(near_sort_kernel, dim3(blocks), dim3(256), 0, s, imgs, near, seg_count, seg_cap, n_seg, res, ctl, jobs,
+              cap_r, counter);
+    CH_LAUNCH(near_eval_kernel, dim3(eval_grid), dim3(256), 0, s, jobs, cap_r, ctl, R, S, n_tot, res, imgs, near,
+              seg_count, seg_cap, n_seg);
+    CH_LAUNCH(near_apply_kernel, dim3(ablocks), dim3(256), 0, s, outs, near, seg_count, seg_cap, n_seg, res);
     return hipSuccess;
 }
 

@@ -12,16 +12,23 @@ hipError_t launch_colsum(hipStream_t s, const ImgDev* imgs, const RowChunk* chun
 hipError_t launch_bias(hipStream_t s, const double* R, const unsigned long long* S, double n_tot, float* bias);
 // Projection: wavefront w appends its near-margin descriptors to
 // near[w * seg_cap ..] and writes their number to seg_count[w] (the fp32 form
-// has one 64-entry segment per wavefront of its grid).
+// has one 64-entry segment per wavefront of its grid).  near_work: the work
+// area of the recompute that follows (the projection clears its control
+// words).
 hipError_t launch_proj_mfma(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
                             int n_tiles, const uint4* frag, const float* bias, float margin, NearEntry* near,
-                            uint32_t* seg_count, uint32_t seg_cap);
+                            uint32_t* seg_count, uint32_t seg_cap, void* near_work);
 hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* outs, const RowChunk* tiles,
                             int n_tiles, const float* R32, const float* bias, float margin, NearEntry* near,
-                            uint32_t* seg_count);
-hipError_t launch_fixup(hipStream_t s, int grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+                            uint32_t* seg_count, void* near_work);
+// Binary64 recompute of the near list's flagged projections (three launches).
+// work: near_work_bytes(n_seg * seg_cap) bytes of device scratch, the one
+// given to the projection launch just before.
+uint32_t near_row_cap(uint64_t n_cap);
+size_t near_work_bytes(uint64_t n_cap);
+hipError_t launch_fixup(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
                         const uint32_t* seg_count, uint32_t seg_cap, uint32_t n_seg, const double* R,
-                        const unsigned long long* S, double n_tot, unsigned long long* counter);
+                        const unsigned long long* S, double n_tot, void* work, unsigned long long* counter);
 hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const TableOut* touts,
                          const int32_t* train_list, int n_train);
 hipError_t launch_match(hipStream_t s, bool epi, int ns, int grid, const ImgDev* imgs, const PairDev* pairs, const Item* items,

@@ -103,6 +103,37 @@ def test_codes_adversarial_near_margin(mats, mode):
     _assert_codes(codes, keys, oc, ok, mode)
 
 
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_codes_every_projection_recomputed(mats, mode):
+    """A margin so wide that every projection is flagged: all 176 bits of
+    every descriptor come from the binary64 recompute, and each row holds
+    more recomputes than its region of the row-sorted job list, so the
+    recompute takes its spread form (jobs of any row per wavefront)."""
+    _say(f"codes, every projection recomputed, mode={mode}")
+    rng = np.random.default_rng(21)
+    ims = [synth.desc(rng, n) for n in (1000, 37, 1, 0, 129)]
+    oc, ok = oracle.build_codes(ims, *mats)
+    m = binding.Matcher(*mats, mode=mode, margin_coef=1e3)
+    _, codes, keys, st = _gpu_codes(m, ims)
+    _assert_codes(codes, keys, oc, ok, mode)
+    assert st["near_margin_recomputes"] == 1167 * 176
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_codes_row_sorted_recompute_many_chunks(mats, mode):
+    """60000 descriptors at the default margin: about 80 recomputes per row,
+    so rows span two or more 64-job chunks of the row-sorted recompute, with
+    room to spare in every row's region."""
+    _say(f"codes, 6 x 10000, mode={mode}")
+    rng = np.random.default_rng(22)
+    ims = [synth.desc(rng, 10000) for _ in range(6)]
+    oc, ok = oracle.build_codes(ims, *mats)
+    m = binding.Matcher(*mats, mode=mode)
+    _, codes, keys, st = _gpu_codes(m, ims)
+    _assert_codes(codes, keys, oc, ok, mode)
+    assert 64 * 176 < st["near_margin_recomputes"] < 60000
+
+
 def test_codes_random_matrices_many_sizes(mats):
     """Other seeds, scaled rows and uneven sizes."""
     for seed in (1, 2, 3):
