@@ -628,7 +628,7 @@ static int run_project(cashash_ctx* c, const std::vector<ImgDev>& imgs, std::vec
     // the recompute: as many wavefronts as the near list has segments, at
     // most 16 per compute unit
     const int fix_grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_seg + 3) / 4, (int64_t)c->n_cu * 4));
-    HIPCHK(launch_fixup(c->stream, fix_grid, dI, dO, near, seg_count, seg_cap, n_seg, c->dR64.as<double>(),
+    HIPCHK(launch_near_recompute(c->stream, fix_grid, dI, dO, near, seg_count, seg_cap, n_seg, c->dR64.as<double>(),
                         c->dS.as<unsigned long long>(), n_tot, work, c->dCount.as<unsigned long long>()));
     return CASHASH_OK;
 }

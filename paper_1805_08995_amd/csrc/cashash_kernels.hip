@@ -786,7 +786,7 @@ size_t near_work_bytes(uint64_t n_cap) {
     return (size_t)kNearCtlWords * 4 + res + (size_t)kRows * near_row_cap(n_cap) * sizeof(NearJob);
 }
 
-hipError_t launch_fixup(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+hipError_t launch_near_recompute(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
                         const uint32_t* seg_count, uint32_t seg_cap, uint32_t n_seg, const double* R,
                         const unsigned long long* S, double n_tot, void* work, unsigned long long* counter) {
     if (n_seg == 0) return hipSuccess;

@@ -26,7 +26,7 @@ hipError_t launch_proj_fp32(hipStream_t s, const ImgDev* imgs, const CodeOut* ou
 // given to the projection launch just before.
 uint32_t near_row_cap(uint64_t n_cap);
 size_t near_work_bytes(uint64_t n_cap);
-hipError_t launch_fixup(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
+hipError_t launch_near_recompute(hipStream_t s, int eval_grid, const ImgDev* imgs, const CodeOut* outs, const NearEntry* near,
                         const uint32_t* seg_count, uint32_t seg_cap, uint32_t n_seg, const double* R,
                         const unsigned long long* S, double n_tot, void* work, unsigned long long* counter);
 hipError_t launch_bucket(hipStream_t s, bool epi, const ImgDev* imgs, const TableOut* touts,

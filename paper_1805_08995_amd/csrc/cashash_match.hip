@@ -599,12 +599,24 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         rb[t] = readfirstlane_u32(qr.qtab[t]) + st[t];
                     }
                 }
+                // Eq. 1-2 for 64 keypoints at once: the compare's lane mask
+                // itself (no branch), ANDed with the run's lanes; positions
+                // past the run are clamped to its last entry (0 for an empty
+                // run), so every load stays inside the table
+                const double rhs = dd * (qr.la * qr.la + qr.lb * qr.lb);
+                uint32_t lastv[kTables];
+#pragma unroll
+                for (int t = 0; t < kTables; ++t) lastv[t] = rl[t] ? rb[t] + rl[t] - 1u : 0u;
                 auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
-                    const bool ok = i0 + (uint32_t)lane < rl[t] && band_ok(kp, qr, dd);
-                    const uint64_t mk = __ballot(ok);
+                    const double xp = (double)kp.x, yp = (double)kp.y;
+                    const double ev = (qr.la * xp + qr.lb * yp) + qr.lc;
+                    const uint32_t left = rl[t] - i0;  // > 0, or 0 for an empty run (i0 = 0)
+                    const uint64_t lm = left >= 64u ? ~0ull : (1ull << left) - 1ull;
+                    const uint64_t mk = __builtin_amdgcn_ballot_w64(ev * ev <= rhs) & lm;
                     if (mk != 0) {  // wave-uniform; most chunks have no survivor
                         const uint32_t sl = n_surv + mbcnt64(mk);
-                        if (ok && sl < (uint32_t)kListCap) list[sl] = ((8u * (uint32_t)t) << 24) | pos;
+                        if (((mk >> lane) & 1ull) && sl < (uint32_t)kListCap)
+                            list[sl] = ((8u * (uint32_t)t) << 24) | pos;
                         n_surv += (uint32_t)__popcll(mk);
                     }
                 };
@@ -612,7 +624,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     uint32_t ps[kTables];
                     float2 kp[kTables];
 #pragma unroll
-                    for (int t = 0; t < kTables; ++t) ps[t] = (uint32_t)lane < rl[t] ? rb[t] + (uint32_t)lane : 0u;
+                    for (int t = 0; t < kTables; ++t) ps[t] = min(rb[t] + (uint32_t)lane, lastv[t]);
 #pragma unroll
                     for (int t = 0; t < kTables; ++t) kp[t] = gload(tv.kp + ps[t]);
 #pragma unroll
@@ -622,7 +634,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 for (int t = 0; t < kTables; ++t) {
                     const uint32_t len = readfirstlane_u32(rl[t]);
                     for (uint32_t i0 = 64; i0 < len; i0 += 64) {
-                        const uint32_t pos = i0 + (uint32_t)lane < len ? rb[t] + i0 + (uint32_t)lane : 0u;
+                        const uint32_t pos = min(rb[t] + i0 + (uint32_t)lane, lastv[t]);
                         band_chunk(t, i0, gload(tv.kp + pos), pos);
                     }
                 }
