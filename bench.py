@@ -396,6 +396,8 @@ def main():
                     help="also run the disk level (set file, host groups within MB megabytes) on the bench set")
     ap.add_argument("--geometric-only", action="store_true",
                     help="run only the two-stage form (for profiling) and print its JSON object")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run only the uneven host-memory leg (for profiling) and print its JSON object")
     ap.add_argument("--epipolar-only", action="store_true",
                     help="run only the epipolar leg (for profiling) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -422,6 +424,9 @@ def main():
     binding.lib()
     if args.geometric_only:
         print(json.dumps(geometric_leg(binding, synth, torch, args.steps, args.cpu_seconds, args.no_cpu)), flush=True)
+        return
+    if args.uneven_only:
+        print(json.dumps(uneven_leg(binding, synth, synth.projection_matrices(), max(args.steps, 1))), flush=True)
         return
     if args.epipolar_only:
         print(json.dumps(epipolar_leg(binding, synth, torch, synth.projection_matrices(), max(args.steps, 1))),

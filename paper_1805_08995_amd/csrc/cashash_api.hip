@@ -430,8 +430,8 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
             hipEventCreateWithFlags(&c->job_ev[j][2], hipEventDisableTiming) != hipSuccess)
             return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
     {
-        // host copy threads: CASHASH_HOST_THREADS, else up to 8 of the host's
-        int nt = (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency()));
+        // host copy threads: CASHASH_HOST_THREADS, else up to 16 of the host's
+        int nt = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
         if (const char* e = std::getenv("CASHASH_HOST_THREADS")) nt = std::max(1, std::min(64, std::atoi(e)));
         c->pool.reset(new WorkPool(nt));
     }
@@ -1215,21 +1215,55 @@ static int finish_match_job(cashash_ctx* c, MatchJob& J, bool whole_stream = tru
 
 // Chunked upload of caller host memory through two pinned buffers on the copy
 // stream: the CPU fills one buffer while the other is in flight.
-static int h2d_staged(cashash_ctx* c, void* dst, const void* src, size_t bytes, int64_t* h2d) {
-    const size_t chunk = (size_t)16 << 20;
+// One array of a block upload: `bytes` from host `src` to offset `off` of the
+// block's device range.
+struct UpPiece {
+    size_t off;
+    const void* src;
+    size_t bytes;
+};
+
+// Uploads a block's arrays (pieces in ascending, non-overlapping offsets) into
+// the device range at dst.  The span from the first piece to the end of the
+// last is staged through the two pinned buffers in windows of 16 MiB: the host
+// threads pack a window from the pieces it overlaps, one copy on the copy
+// stream sends it, and the next window is packed into the other buffer while
+// it travels.  Bytes of the span between pieces (alignment padding, or areas
+// that kernels write later) carry whatever the buffer held.  A block of many
+// small images so costs a few large copies, not one copy and one wait per
+// array.
+static int h2d_block(cashash_ctx* c, uint8_t* dst, const std::vector<UpPiece>& pieces, int64_t* h2d) {
+    if (pieces.empty()) return CASHASH_OK;
+    const size_t chunk = (size_t)16 << 20, grain = (size_t)1 << 20;
     RETCHK(c->pin[0].ensure(chunk));
     RETCHK(c->pin[1].ensure(chunk));
-    for (size_t off = 0; off < bytes; off += chunk) {
+    const size_t lo = pieces.front().off, hi = pieces.back().off + pieces.back().bytes;
+    struct Seg {
+        size_t at;
+        const uint8_t* src;
+        size_t n;
+    };
+    std::vector<Seg> segs;
+    size_t pi = 0;
+    for (size_t w0 = lo; w0 < hi; w0 += chunk) {
+        const size_t w1 = std::min(hi, w0 + chunk);
         const int b = c->pin_turn;
         c->pin_turn ^= 1;
         HIPCHK(hipEventSynchronize(c->pin_ev[b]));
-        const size_t n = std::min(chunk, bytes - off);
-        parallel_copy(*c->pool, c->pin[b].p, static_cast<const uint8_t*>(src) + off, n);
-        HIPCHK(hipMemcpyAsync(static_cast<uint8_t*>(dst) + off, c->pin[b].p, n, hipMemcpyHostToDevice,
-                              c->copy_stream));
+        segs.clear();
+        while (pi < pieces.size() && pieces[pi].off + pieces[pi].bytes <= w0) ++pi;
+        for (size_t k = pi; k < pieces.size() && pieces[k].off < w1; ++k) {
+            const size_t a = std::max(pieces[k].off, w0), e = std::min(pieces[k].off + pieces[k].bytes, w1);
+            for (size_t g = a; g < e; g += grain)
+                segs.push_back(Seg{g - w0, static_cast<const uint8_t*>(pieces[k].src) + (g - pieces[k].off),
+                                   std::min(grain, e - g)});
+        }
+        uint8_t* pb = static_cast<uint8_t*>(c->pin[b].p);
+        c->pool->run((int64_t)segs.size(), [&](int64_t i) { std::memcpy(pb + segs[i].at, segs[i].src, segs[i].n); });
+        HIPCHK(hipMemcpyAsync(dst + w0, pb, w1 - w0, hipMemcpyHostToDevice, c->copy_stream));
         HIPCHK(hipEventRecord(c->pin_ev[b], c->copy_stream));
     }
-    if (h2d) *h2d += (int64_t)bytes;
+    for (const UpPiece& p : pieces) *h2d += (int64_t)p.bytes;
     return CASHASH_OK;
 }
 
@@ -1304,14 +1338,15 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
     auto load = [&](int b, int s) -> int {
         if (resident[s] == b) return CASHASH_OK;
         HIPCHK(hipStreamWaitEvent(c->copy_stream, c->slot_free_ev[s], 0));
-        size_t off = (size_t)s * slot;
+        std::vector<UpPiece> pieces;
+        size_t off = 0;
         for (int m = first[b]; m < first[b + 1]; ++m) {
-            place[m] = off;
-            if (im->n_feat[m] > 0)
-                RETCHK(h2d_staged(c, c->stage.as<uint8_t>() + off, im->desc[m], (size_t)im->n_feat[m] * kDim, &h2d));
+            place[m] = (size_t)s * slot + off;
+            if (im->n_feat[m] > 0) pieces.push_back(UpPiece{off, im->desc[m], (size_t)im->n_feat[m] * kDim});
             off += (size_t)bytes[m];
             loads++;
         }
+        RETCHK(h2d_block(c, c->stage.as<uint8_t>() + (size_t)s * slot, pieces, &h2d));
         HIPCHK(hipEventRecord(c->slot_load_ev[s], c->copy_stream));
         resident[s] = b;
         return CASHASH_OK;
@@ -1398,6 +1433,10 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
 // missing blocks are loaded into free slots of three, the next step's new
 // block is prefetched while the current step computes, and each step's
 // outputs come back through pinned memory.
+// Host-memory matching runs a scheduler step's pairs in parts of at most
+// this many queries (12 output bytes each).
+constexpr int64_t kSubQueries = (int64_t)1 << 24;
+
 static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
                       const uint8_t* const* keys, const float* const* kp, MatchJob& J, int32_t* o_idx,
                       int32_t* o_d1, int32_t* o_d2, cashash_stats* stats) {
@@ -1431,22 +1470,23 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
     int64_t h2d = 0, d2h = 0, loads = 0;
     auto load_block = [&](int b, int s) -> int {
         HIPCHK(hipStreamWaitEvent(c->copy_stream, c->slot_free_ev[s], 0));
-        size_t off = (size_t)s * slot;
+        std::vector<UpPiece> pieces;
+        size_t off = 0;
         for (int i = S.block_first[b]; i < S.block_first[b + 1]; ++i) {
             const int m = S.block_images[i];
             const size_t n = (size_t)im->n_feat[m];
             const SlotImage L = slot_layout((int)n, true, J.epi);
-            uint8_t* base = c->stage.as<uint8_t>() + off;
-            place[m] = off;
+            place[m] = (size_t)s * slot + off;
             if (n) {
-                RETCHK(h2d_staged(c, base + L.desc, im->desc[m], n * kDim, &h2d));
-                RETCHK(h2d_staged(c, base + L.codes, codes[m], n * 16, &h2d));
-                RETCHK(h2d_staged(c, base + L.keys, keys[m], n * 6, &h2d));
-                if (J.epi) RETCHK(h2d_staged(c, base + L.kp, kp[m], n * 8, &h2d));
+                pieces.push_back(UpPiece{off + L.desc, im->desc[m], n * kDim});
+                pieces.push_back(UpPiece{off + L.codes, codes[m], n * 16});
+                pieces.push_back(UpPiece{off + L.keys, keys[m], n * 6});
+                if (J.epi) pieces.push_back(UpPiece{off + L.kp, kp[m], n * 8});
             }
             off += (size_t)data_bytes[m];
             loads++;
         }
+        RETCHK(h2d_block(c, c->stage.as<uint8_t>() + (size_t)s * slot, pieces, &h2d));
         HIPCHK(hipEventRecord(c->slot_load_ev[s], c->copy_stream));
         slot_block[s] = b;
         return CASHASH_OK;
@@ -1472,7 +1512,7 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
     struct Pending {
         bool valid = false;
         MatchJob job;
-        size_t step = 0;
+        std::vector<int64_t> pairs;  // its pairs (indices into the call's pair list)
         int64_t nq = 0;
     } pending;
     auto drain = [&](Pending& pd) -> int {
@@ -1480,10 +1520,9 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         MatchJob& Jp = pd.job;
         RETCHK(finish_match_job(c, Jp, false));
         const int32_t* ho = reinterpret_cast<const int32_t*>(c->pin_out[Jp.turn].p);
-        const SchedStep& sp = S.steps[pd.step];
         const int64_t nqp = pd.nq;
         c->pool->run((int64_t)Jp.pair_q.size(), [&](int64_t i) {
-            const int64_t p = S.order[sp.pair_begin + i];
+            const int64_t p = pd.pairs[i];
             const int64_t n = im->n_feat[J.pair_q[p]];
             if (!n) return;
             std::memcpy(o_idx + J.pair_out[p], ho + Jp.pair_out[i], (size_t)n * 4);
@@ -1507,62 +1546,76 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[si], 0));
         HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[sk], 0));
         slot_used_at[si] = slot_used_at[sk] = (int64_t)st;
-        MatchJob Js;
-        Js.epi = J.epi;
-        Js.max_px = J.max_px;
-        Js.imgs.assign(M, ImgDev{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0});
+        std::vector<ImgDev> views(M, ImgDev{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0});
         for (int b : {step.bi, step.bk})
             for (int i = S.block_first[b]; i < S.block_first[b + 1]; ++i) {
                 const int m = S.block_images[i];
                 const int n = im->n_feat[m];
                 const SlotImage L = slot_layout(n, true, J.epi);
                 uint8_t* base = c->stage.as<uint8_t>() + place[m];
-                Js.imgs[m] = ImgDev{base + L.desc, reinterpret_cast<const uint64_t*>(base + L.codes), base + L.keys,
-                                    J.epi ? reinterpret_cast<const float*>(base + L.kp) : nullptr, nullptr, nullptr,
-                                    n, 0};
+                views[m] = ImgDev{base + L.desc, reinterpret_cast<const uint64_t*>(base + L.codes), base + L.keys,
+                                  J.epi ? reinterpret_cast<const float*>(base + L.kp) : nullptr, nullptr, nullptr, n,
+                                  0};
             }
-        std::vector<double> Fs;
-        int64_t nq = 0;
-        for (int64_t i = step.pair_begin; i < step.pair_end; ++i) {
-            const int64_t p = S.order[i];
-            Js.pair_q.push_back(J.pair_q[p]);
-            Js.pair_t.push_back(J.pair_t[p]);
-            Js.pair_out.push_back(nq);
-            nq += im->n_feat[J.pair_q[p]];
-            if (J.epi) Fs.insert(Fs.end(), J.F + 9 * p, J.F + 9 * p + 9);
-        }
-        Js.F = J.epi ? Fs.data() : nullptr;
-        const int turn = c->job_turn;  // the slot launch_match_job takes
-        RETCHK(c->outbuf[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
-        Js.o_idx = c->outbuf[turn].as<int32_t>();
-        Js.o_d1 = Js.o_idx + nq;
-        Js.o_d2 = Js.o_d1 + nq;
-        RETCHK(c->pin_out[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
-        RETCHK(launch_match_job(c, Js));
-        HIPCHK(hipEventRecord(c->slot_free_ev[si], c->stream));
-        HIPCHK(hipEventRecord(c->slot_free_ev[sk], c->stream));
-        if (nq)
-            HIPCHK(hipMemcpyAsync(c->pin_out[Js.turn].p, c->outbuf[Js.turn].p, (size_t)nq * 12,
-                                  hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipEventRecord(c->job_ev[Js.turn][2], c->stream));
-        // prefetch the next step's new block while this one computes
-        if (st + 1 < S.steps.size()) {
-            const SchedStep& nx = S.steps[st + 1];
-            for (int b : {nx.bi, nx.bk}) {
-                if (slot_of(b) >= 0) continue;
-                const int s = pick_slot(step.bi, step.bk);
-                if (s < 0) break;
-                RETCHK(load_block(b, s));
-                break;  // one block ahead
+        // the step's pairs, grouped by train image (each part builds the
+        // bucket tables of its own train images), in parts of at most
+        // kSubQueries queries, so that a part's download and copy-out overlap
+        // the next part's kernels
+        std::vector<int64_t> ord(S.order.begin() + step.pair_begin, S.order.begin() + step.pair_end);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return J.pair_t[x] < J.pair_t[y]; });
+        for (size_t pb = 0; pb < ord.size();) {
+            size_t pe = pb;
+            int64_t nq = 0;
+            while (pe < ord.size() && (pe == pb || nq + im->n_feat[J.pair_q[ord[pe]]] <= kSubQueries))
+                nq += im->n_feat[J.pair_q[ord[pe++]]];
+            MatchJob Js;
+            Js.epi = J.epi;
+            Js.max_px = J.max_px;
+            Js.imgs = views;
+            std::vector<double> Fs;
+            int64_t q_at = 0;
+            for (size_t i = pb; i < pe; ++i) {
+                const int64_t p = ord[i];
+                Js.pair_q.push_back(J.pair_q[p]);
+                Js.pair_t.push_back(J.pair_t[p]);
+                Js.pair_out.push_back(q_at);
+                q_at += im->n_feat[J.pair_q[p]];
+                if (J.epi) Fs.insert(Fs.end(), J.F + 9 * p, J.F + 9 * p + 9);
             }
+            Js.F = J.epi ? Fs.data() : nullptr;
+            const int turn = c->job_turn;  // the slot launch_match_job takes
+            RETCHK(c->outbuf[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
+            Js.o_idx = c->outbuf[turn].as<int32_t>();
+            Js.o_d1 = Js.o_idx + nq;
+            Js.o_d2 = Js.o_d1 + nq;
+            RETCHK(c->pin_out[turn].ensure((size_t)std::max<int64_t>(nq, 1) * 12));
+            RETCHK(launch_match_job(c, Js));
+            HIPCHK(hipEventRecord(c->slot_free_ev[si], c->stream));
+            HIPCHK(hipEventRecord(c->slot_free_ev[sk], c->stream));
+            if (nq)
+                HIPCHK(hipMemcpyAsync(c->pin_out[Js.turn].p, c->outbuf[Js.turn].p, (size_t)nq * 12,
+                                      hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(c->job_ev[Js.turn][2], c->stream));
+            // prefetch the next step's new block while this one computes
+            if (pb == 0 && st + 1 < S.steps.size()) {
+                const SchedStep& nx = S.steps[st + 1];
+                for (int b : {nx.bi, nx.bk}) {
+                    if (slot_of(b) >= 0) continue;
+                    const int s = pick_slot(step.bi, step.bk);
+                    if (s < 0) break;
+                    RETCHK(load_block(b, s));
+                    break;  // one block ahead
+                }
+            }
+            // the previous part's results go to the caller while this one computes
+            if (pending.valid) RETCHK(drain(pending));
+            pending.valid = true;
+            pending.job = std::move(Js);
+            pending.job.F = nullptr;  // Fs ends with this part; the job's pair table holds F already
+            pending.pairs.assign(ord.begin() + pb, ord.begin() + pe);
+            pending.nq = nq;
+            pb = pe;
         }
-        // the previous step's results go to the caller while this one computes
-        if (pending.valid) RETCHK(drain(pending));
-        pending.valid = true;
-        pending.job = std::move(Js);
-        pending.job.F = nullptr;  // Fs ends with this step; the job's pair table holds F already
-        pending.step = st;
-        pending.nq = nq;
     }
     if (pending.valid) RETCHK(drain(pending));
     if (stats) {
