@@ -1309,7 +1309,7 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
         const int n = im->n_feat[m];
         if (n > 0 && (!im->desc[m] || ((passes & kPassCodes) && (!codes_out[m] || !keys_out[m]))))
             return fail(CASHASH_E_INVAL, "image %d: null descriptor or output pointer", m);
-        bytes[m] = (int64_t)slot_layout(n, true, false).end;
+        bytes[m] = (int64_t)al256((size_t)n * kDim);  // descriptors only: codes go to an output area
         n_tot += n;
     }
     *near_count = 0;
@@ -1351,15 +1351,20 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
         resident[s] = b;
         return CASHASH_OK;
     };
-    auto views = [&](int b, std::vector<ImgDev>& iv, std::vector<CodeOut>& ov) {
+    // image views of block b; with out, the codes and keys of its images go to
+    // one device output area (image i's codes at pos[i], its keys right after)
+    // that comes back with a single copy
+    std::vector<size_t> pos;
+    auto views = [&](int b, std::vector<ImgDev>& iv, std::vector<CodeOut>* ov, uint8_t* out) {
         iv.clear();
-        ov.clear();
+        if (ov) ov->clear();
+        pos.assign(1, 0);
         for (int m = first[b]; m < first[b + 1]; ++m) {
             const int n = im->n_feat[m];
-            const SlotImage L = slot_layout(n, true, false);
-            uint8_t* base = c->stage.as<uint8_t>() + place[m];
-            iv.push_back(ImgDev{base + L.desc, nullptr, nullptr, nullptr, nullptr, nullptr, n, 0});
-            ov.push_back(CodeOut{reinterpret_cast<uint64_t*>(base + L.codes), base + L.keys, 0});
+            iv.push_back(ImgDev{c->stage.as<uint8_t>() + place[m], nullptr, nullptr, nullptr, nullptr, nullptr, n, 0});
+            const size_t at = pos.back();
+            if (ov) ov->push_back(CodeOut{reinterpret_cast<uint64_t*>(out + at), out + at + (size_t)n * 16, 0});
+            pos.push_back(at + (((size_t)n * 22 + 15) & ~size_t(15)));  // codes stay 16-byte aligned
         }
     };
     std::vector<ImgDev> iv;
@@ -1373,7 +1378,7 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
             const int s = b & 1;
             RETCHK(load(b, s));
             HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
-            views(b, iv, ov);
+            views(b, iv, nullptr, nullptr);
             RETCHK(run_colsum(c, iv));
             HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
             if (b + 1 < nb) RETCHK(load(b + 1, (b + 1) & 1));  // prefetch while the sums run
@@ -1386,27 +1391,15 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
         int s = resident[0] == b ? 0 : resident[1] == b ? 1 : (b & 1);
         RETCHK(load(b, s));
         HIPCHK(hipStreamWaitEvent(c->stream, c->slot_load_ev[s], 0));
-        views(b, iv, ov);
-        RETCHK(run_project(c, iv, ov, both ? n_tot : n_tot_set));
         size_t out_bytes = 0;
-        for (int m = first[b]; m < first[b + 1]; ++m) out_bytes += (size_t)im->n_feat[m] * 22;
-        RETCHK(c->pin_out[0].ensure(out_bytes));
-        size_t po = 0;
-        for (int m = first[b]; m < first[b + 1]; ++m) {
-            const size_t n = (size_t)im->n_feat[m];
-            if (!n) continue;
-            const SlotImage L = slot_layout((int)n, true, false);
-            uint8_t* base = c->stage.as<uint8_t>() + place[m];
-            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out[0].p + po, base + L.codes, n * 16, hipMemcpyDeviceToHost,
-                                  c->stream));
-            HIPCHK(hipMemcpyAsync((uint8_t*)c->pin_out[0].p + po + n * 16, base + L.keys, n * 6,
-                                  hipMemcpyDeviceToHost, c->stream));
-            po += n * 22;
-        }
+        for (int m = first[b]; m < first[b + 1]; ++m) out_bytes += (((size_t)im->n_feat[m] * 22 + 15) & ~size_t(15));
+        RETCHK(c->outbuf[0].ensure(std::max<size_t>(out_bytes, 16)));
+        RETCHK(c->pin_out[0].ensure(std::max<size_t>(out_bytes, 16)));
+        views(b, iv, &ov, c->outbuf[0].as<uint8_t>());
+        RETCHK(run_project(c, iv, ov, both ? n_tot : n_tot_set));
         HIPCHK(hipEventRecord(c->slot_free_ev[s], c->stream));
+        HIPCHK(hipMemcpyAsync(c->pin_out[0].p, c->outbuf[0].p, out_bytes, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        std::vector<size_t> pos(first[b + 1] - first[b] + 1, 0);
-        for (int m = first[b]; m < first[b + 1]; ++m) pos[m - first[b] + 1] = pos[m - first[b]] + (size_t)im->n_feat[m] * 22;
         const uint8_t* ho = static_cast<const uint8_t*>(c->pin_out[0].p);
         c->pool->run(first[b + 1] - first[b], [&](int64_t i) {
             const int m = first[b] + (int)i;
@@ -1415,7 +1408,7 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
             std::memcpy(codes_out[m], ho + pos[i], n * 16);
             std::memcpy(keys_out[m], ho + pos[i] + n * 16, n * 6);
         });
-        d2h += (int64_t)pos.back();
+        for (int m = first[b]; m < first[b + 1]; ++m) d2h += (int64_t)im->n_feat[m] * 22;
     }
     unsigned long long cnt = 0;
     HIPCHK(hipStreamSynchronize(c->stream));
