@@ -1566,12 +1566,20 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
                                   J.epi ? reinterpret_cast<const float*>(base + L.kp) : nullptr, nullptr, nullptr, n,
                                   0};
             }
-        // the step's pairs, grouped by train image (each part builds the
-        // bucket tables of its own train images), in parts of at most
-        // kSubQueries queries, so that a part's download and copy-out overlap
-        // the next part's kernels
+        // the step's pairs, grouped by register-slot group (a part of one
+        // group is one persistent launch, not up to three) and then by train
+        // image (each part builds the bucket tables of its own train images),
+        // in parts of at most kSubQueries queries, so that a part's download
+        // and copy-out overlap the next part's kernels
         std::vector<int64_t> ord(S.order.begin() + step.pair_begin, S.order.begin() + step.pair_end);
-        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return J.pair_t[x] < J.pair_t[y]; });
+        auto group = [&](int64_t p) {
+            const int n = im->n_feat[J.pair_t[p]];
+            return J.epi || n <= kLargeTrain ? 0 : n <= kHugeTrain ? 1 : 2;
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+            const int gx = group(x), gy = group(y);
+            return gx != gy ? gx < gy : J.pair_t[x] < J.pair_t[y];
+        });
         for (size_t pb = 0; pb < ord.size();) {
             size_t pe = pb;
             int64_t nq = 0;
