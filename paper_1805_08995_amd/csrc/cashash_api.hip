@@ -1002,6 +1002,10 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullp
         tbytes += ent_bytes(J.imgs[m].n, J.epi);
         tbytes = (tbytes + 255) & ~size_t(255);
     }
+    // the band kernel reads whole 64-entry chunks of keypoints from a run's
+    // start (lanes past the run are masked): up to 64 entries past the last
+    // table's end
+    if (J.epi) tbytes += 512;
     // the pair plan (host work): visiting order, launch shapes, per-shape tile
     // tables and the pair table.  Batched: items ordered by train image, so
     // the waves running together share one train image's tables in L2.

@@ -600,18 +600,18 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     }
                 }
                 // Eq. 1-2 for 64 keypoints at once: the compare's lane mask
-                // itself (no branch), ANDed with the run's lanes; positions
-                // past the run are clamped to its last entry (0 for an empty
-                // run), so every load stays inside the table
+                // itself (no branch), ANDed with the run's lanes (a vector
+                // compare: cheaper here than building the mask from the run
+                // length with scalar shifts).  Lanes past the run read the
+                // entries after it, unclamped: at most 64 entries past the
+                // keypoints of the last table, inside the 512 bytes the
+                // tables of a band call keep at their end; their results are
+                // masked out
                 const double rhs = dd * (qr.la * qr.la + qr.lb * qr.lb);
-                uint32_t lastv[kTables];
-#pragma unroll
-                for (int t = 0; t < kTables; ++t) lastv[t] = rl[t] ? rb[t] + rl[t] - 1u : 0u;
                 auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
                     const double xp = (double)kp.x, yp = (double)kp.y;
                     const double ev = (qr.la * xp + qr.lb * yp) + qr.lc;
-                    const uint32_t left = rl[t] - i0;  // > 0, or 0 for an empty run (i0 = 0)
-                    const uint64_t lm = left >= 64u ? ~0ull : (1ull << left) - 1ull;
+                    const uint64_t lm = __builtin_amdgcn_ballot_w64(i0 + (uint32_t)lane < rl[t]);
                     const uint64_t mk = __builtin_amdgcn_ballot_w64(ev * ev <= rhs) & lm;
                     if (mk != 0) {  // wave-uniform; most chunks have no survivor
                         const uint32_t sl = n_surv + mbcnt64(mk);
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     uint32_t ps[kTables];
                     float2 kp[kTables];
 #pragma unroll
-                    for (int t = 0; t < kTables; ++t) ps[t] = min(rb[t] + (uint32_t)lane, lastv[t]);
+                    for (int t = 0; t < kTables; ++t) ps[t] = rb[t] + (uint32_t)lane;
 #pragma unroll
                     for (int t = 0; t < kTables; ++t) kp[t] = gload(tv.kp + ps[t]);
 #pragma unroll
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 for (int t = 0; t < kTables; ++t) {
                     const uint32_t len = readfirstlane_u32(rl[t]);
                     for (uint32_t i0 = 64; i0 < len; i0 += 64) {
-                        const uint32_t pos = min(rb[t] + i0 + (uint32_t)lane, lastv[t]);
+                        const uint32_t pos = rb[t] + i0 + (uint32_t)lane;
                         band_chunk(t, i0, gload(tv.kp + pos), pos);
                     }
                 }
