@@ -45,10 +45,10 @@ HBM_PEAK_GBS = 8000.0
 # SQ_INSTS_VALU.  Valid only for the matcher sources they were taken on
 # (sha256 over MATCHER_SOURCES, in order); null otherwise.
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_COUNTERS = {"sources_sha256": "5084e236fb77d10572d7cc0b68bf10f483477659eddff8faf1b3aca8d50f753d",
+MEASURED_COUNTERS = {"sources_sha256": "8b94f127dbd5c086c577b6403a6752916ec54e67a87331bf5638836daac387d8",
                      "workload": "scenes_100x8000_exhaustive_4950pairs",
-                     "fetch_bytes": int(4482383.4 * 1024 * 2), "write_bytes": int(479167.5 * 1024),
-                     "valu_insts": 8436682573}
+                     "fetch_bytes": int(4424796.6 * 1024 * 2), "write_bytes": int(479173.2 * 1024),
+                     "valu_insts": 8436679479}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles (16 lanes per cycle), 2.4 GHz: 614.4 G instructions/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

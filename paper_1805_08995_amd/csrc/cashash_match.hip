@@ -608,14 +608,22 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 // tables of a band call keep at their end; their results are
                 // masked out
                 const double rhs = dd * (qr.la * qr.la + qr.lb * qr.lb);
+                // keypoint of entry pos: a 32-bit byte offset from the table's
+                // base (the scalar-base load form, no 64-bit address per lane)
+                auto kp_at = [&](uint32_t pos) {
+                    return reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tv.kp) + (pos << 3));
+                };
                 auto band_chunk = [&](int t, uint32_t i0, float2 kp, uint32_t pos) {
                     const double xp = (double)kp.x, yp = (double)kp.y;
                     const double ev = (qr.la * xp + qr.lb * yp) + qr.lc;
-                    const uint64_t lm = __builtin_amdgcn_ballot_w64(i0 + (uint32_t)lane < rl[t]);
-                    const uint64_t mk = __builtin_amdgcn_ballot_w64(ev * ev <= rhs) & lm;
+                    const bool in_run = i0 + (uint32_t)lane < rl[t];
+                    const bool in_band = ev * ev <= rhs;
+                    const uint64_t mk = __builtin_amdgcn_ballot_w64(in_band) & __builtin_amdgcn_ballot_w64(in_run);
                     if (mk != 0) {  // wave-uniform; most chunks have no survivor
                         const uint32_t sl = n_surv + mbcnt64(mk);
-                        if (((mk >> lane) & 1ull) && sl < (uint32_t)kListCap)
+                        // a lane's own survival from its compares, not from
+                        // its bit of mk (no 64-bit shift and test per lane)
+                        if (in_band && in_run && sl < (uint32_t)kListCap)
                             list[sl] = ((8u * (uint32_t)t) << 24) | pos;
                         n_surv += (uint32_t)__popcll(mk);
                     }
@@ -626,7 +634,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
 #pragma unroll
                     for (int t = 0; t < kTables; ++t) ps[t] = rb[t] + (uint32_t)lane;
 #pragma unroll
-                    for (int t = 0; t < kTables; ++t) kp[t] = gload(tv.kp + ps[t]);
+                    for (int t = 0; t < kTables; ++t) kp[t] = gload(kp_at(ps[t]));
 #pragma unroll
                     for (int t = 0; t < kTables; ++t) band_chunk(t, 0u, kp[t], ps[t]);
                 }
@@ -635,7 +643,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     const uint32_t len = readfirstlane_u32(rl[t]);
                     for (uint32_t i0 = 64; i0 < len; i0 += 64) {
                         const uint32_t pos = rb[t] + i0 + (uint32_t)lane;
-                        band_chunk(t, i0, gload(tv.kp + pos), pos);
+                        band_chunk(t, i0, gload(kp_at(pos)), pos);
                     }
                 }
                 wave_sync();
