@@ -143,6 +143,10 @@ struct cashash_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t copy_stream = nullptr;
+    // host-memory mode: output downloads, apart from the uploads on
+    // copy_stream, so that both directions of the link are busy at once and
+    // a part's download overlaps the next part's kernels
+    hipStream_t d2h_stream = nullptr;
     int n_cu = 256;
     std::vector<double> R64;  // [176][128]
     DevBuf dR64, dR32, dFrag, dBias, dS, dCount;
@@ -173,6 +177,7 @@ struct cashash_ctx {
     // per match job in flight (host-memory mode keeps two): kernel start and
     // end, and the end of its output download
     hipEvent_t job_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    hipEvent_t part_ev[2] = {nullptr, nullptr};  // host-memory mode: a part's kernels are done
     int job_turn = 0;
     std::unique_ptr<WorkPool> pool;  // host threads of the bulk host copies
     double last_ms = 0.0;
@@ -211,6 +216,7 @@ static void quiesce(const cashash_ctx* c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->copy_stream) hipStreamSynchronize(c->copy_stream);
+    if (c->d2h_stream) hipStreamSynchronize(c->d2h_stream);
 }
 
 static std::vector<DevBuf*> dev_bufs(cashash_ctx* c) {
@@ -305,10 +311,11 @@ extern "C" const char* cashash_last_error(void) { return g_err.c_str(); }
 static void destroy_ctx(cashash_ctx* c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
-    if (c->copy_stream) {
-        hipStreamSynchronize(c->copy_stream);
-        hipStreamDestroy(c->copy_stream);
-    }
+    for (hipStream_t* st : {&c->copy_stream, &c->d2h_stream})
+        if (*st) {
+            hipStreamSynchronize(*st);
+            hipStreamDestroy(*st);
+        }
     for (DevBuf* b : dev_bufs(c)) b->release();
     for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
                           &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out[0], &c->pin_out[1],
@@ -319,7 +326,8 @@ static void destroy_ctx(cashash_ctx* c) {
                          c->geo_ev[4], c->pin_ev[0], c->pin_ev[1],
                          c->slot_load_ev[0], c->slot_load_ev[1], c->slot_load_ev[2], c->slot_free_ev[0],
                          c->slot_free_ev[1], c->slot_free_ev[2], c->caller_ev, c->job_ev[0][0], c->job_ev[0][1],
-                         c->job_ev[0][2], c->job_ev[1][0], c->job_ev[1][1], c->job_ev[1][2]})
+                         c->job_ev[0][2], c->job_ev[1][0], c->job_ev[1][1], c->job_ev[1][2], c->part_ev[0],
+                         c->part_ev[1]})
         if (e) hipEventDestroy(e);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -423,6 +431,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     int r = cashash_set_config(c, &n);
     if (r) return bail(r);
     if (hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->d2h_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
         return bail(fail(CASHASH_E_DEVICE, "stream/event creation failed"));
     for (int i = 0; i < 5; ++i)
@@ -440,7 +449,7 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     for (hipEvent_t* e : {&c->meta_ev[0][0], &c->meta_ev[0][1], &c->meta_ev[1][0], &c->meta_ev[1][1],
                           &c->meta_ev[2][0], &c->meta_ev[2][1], &c->pin_ev[0], &c->pin_ev[1], &c->slot_load_ev[0],
                           &c->slot_load_ev[1], &c->slot_load_ev[2], &c->slot_free_ev[0], &c->slot_free_ev[1],
-                          &c->slot_free_ev[2], &c->caller_ev})
+                          &c->slot_free_ev[2], &c->caller_ev, &c->part_ev[0], &c->part_ev[1]})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
             return bail(fail(CASHASH_E_DEVICE, "event creation failed"));
     if ((r = c->pin_small.ensure(4096))) return bail(r);
@@ -1450,6 +1459,17 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
 // this many queries (12 output bytes each).
 constexpr int64_t kSubQueries = (int64_t)1 << 24;
 
+// The part size: kSubQueries, or a smaller one from CASHASH_PART_QUERIES (so
+// that small inputs can run as many parts, as tests do).
+static int64_t part_queries() {
+    const char* e = std::getenv("CASHASH_PART_QUERIES");
+    if (e && e[0]) {
+        const long long v = std::atoll(e);
+        if (v >= 1 && v < kSubQueries) return (int64_t)v;
+    }
+    return kSubQueries;
+}
+
 static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
                       const uint8_t* const* keys, const float* const* kp, MatchJob& J, int32_t* o_idx,
                       int32_t* o_d1, int32_t* o_d2, cashash_stats* stats) {
@@ -1519,6 +1539,7 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         return -1;
     };
     c->last_ms = 0.0;
+    const int64_t part_max = part_queries();
     // a step whose kernels and download are queued; its outputs are copied
     // into the caller's arrays (over the host threads) once the next step is
     // queued behind it
@@ -1587,7 +1608,7 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         for (size_t pb = 0; pb < ord.size();) {
             size_t pe = pb;
             int64_t nq = 0;
-            while (pe < ord.size() && (pe == pb || nq + im->n_feat[J.pair_q[ord[pe]]] <= kSubQueries))
+            while (pe < ord.size() && (pe == pb || nq + im->n_feat[J.pair_q[ord[pe]]] <= part_max))
                 nq += im->n_feat[J.pair_q[ord[pe++]]];
             MatchJob Js;
             Js.epi = J.epi;
@@ -1613,10 +1634,17 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
             RETCHK(launch_match_job(c, Js));
             HIPCHK(hipEventRecord(c->slot_free_ev[si], c->stream));
             HIPCHK(hipEventRecord(c->slot_free_ev[sk], c->stream));
+            // the download runs on its own stream once the part's kernels
+            // (and its statistics copy) are done, while the next part's
+            // kernels run.  Both buffers of this turn are free: the host
+            // drained the part that last used them before this part was
+            // queued (drain waits for that part's download)
+            HIPCHK(hipEventRecord(c->part_ev[Js.turn], c->stream));
+            HIPCHK(hipStreamWaitEvent(c->d2h_stream, c->part_ev[Js.turn], 0));
             if (nq)
                 HIPCHK(hipMemcpyAsync(c->pin_out[Js.turn].p, c->outbuf[Js.turn].p, (size_t)nq * 12,
-                                      hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(hipEventRecord(c->job_ev[Js.turn][2], c->stream));
+                                      hipMemcpyDeviceToHost, c->d2h_stream));
+            HIPCHK(hipEventRecord(c->job_ev[Js.turn][2], c->d2h_stream));
             // prefetch the next step's new block while this one computes
             if (pb == 0 && st + 1 < S.steps.size()) {
                 const SchedStep& nx = S.steps[st + 1];

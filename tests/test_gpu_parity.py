@@ -400,6 +400,27 @@ def test_host_memory_mode_streams_blocks(mats, budget):
         assert st["image_loads"] > len(w.images)
 
 
+@pytest.mark.parametrize("budget", [0, 6_000_000])
+def test_host_memory_many_parts(mats, monkeypatch, budget):
+    """Host mode with each scheduler step split into many small parts (the
+    part size lowered from 2^24 queries to 2500): every part's download runs
+    on its own stream while the next part computes, on two alternating output
+    buffers; ragged image sizes give parts of uneven length.  The outputs
+    equal the oracle's, over two calls in a row."""
+    _say(f"host mode, small parts, budget={budget}")
+    w = synth.uneven_set(seed=12, n_images=24, lo=300, hi=3000, n_scenes=4, n_partners=5)
+    oc, ok = oracle.build_codes(w.images, *mats)
+    exp = _oracle_all(w.images, oc, ok, w.pairs, k=10)
+    monkeypatch.setenv("CASHASH_PART_QUERIES", "2500")
+    m = binding.Matcher(*mats, mem="host", device_budget_bytes=budget)
+    for call in range(2):
+        got, st = m.match_pairs(w.images, oc, ok, w.pairs)
+        _assert_match(got, exp, f"host small parts budget {budget} call {call}")
+        assert st["d2h_bytes"] == 12 * st["queries"]
+        if budget:
+            assert st["image_loads"] > len(w.images)  # blocks streamed and reloaded
+
+
 def test_host_memory_epipolar(mats):
     w = synth.epipolar_set(seed=11, n_images=6, n_feat=1200, n_points=8000, n_neighbours=2)
     oc, ok = oracle.build_codes(w.images, *mats)
