@@ -400,6 +400,8 @@ def main():
                     help="run only the uneven host-memory leg (for profiling) and print its JSON object")
     ap.add_argument("--epipolar-only", action="store_true",
                     help="run only the epipolar leg (for profiling) and print its JSON object")
+    ap.add_argument("--host-buffers-only", action="store_true",
+                    help="run only the host-buffer leg on the bench set (for profiling) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -438,6 +440,9 @@ def main():
     w = synth.scene_set(n_images=args.images, n_feat=args.feats)
     mats = synth.projection_matrices()
     log(f"generated in {time.perf_counter() - t0:.1f}s; {len(w.pairs)} pairs")
+    if args.host_buffers_only:
+        print(json.dumps(host_buffers_leg(binding, w, mats, max(args.steps, 1))), flush=True)
+        return
     n_pairs = len(w.pairs)
     # inputs resident in HBM before timing
     flat = torch.from_numpy(np.concatenate(w.images)).cuda()
