@@ -718,14 +718,17 @@ struct MatchJob {
 // A launch shape is the number of queries per work item (one wavefront takes
 // one item at a time) and, for the persistent batched launch, the number of
 // resident blocks per compute unit.  A tile's kept candidates must fit the
-// per-wave tile list: qt * k <= kSelCap.
+// per-wave tile list: qt * k <= kSelCap (kSelCapEpi for the band kernel, which
+// also tries 7 blocks per compute unit, the occupancy it is compiled for).
 
-static std::vector<Shape> shape_candidates(int k, bool batched) {
+static int sel_cap(bool epi) { return epi ? kSelCapEpi : kSelCap; }
+
+static std::vector<Shape> shape_candidates(int k, bool batched, bool epi) {
     std::vector<Shape> v;
-    const int qmax = std::min(kMaxTile, kSelCap / k);
+    const int qmax = std::min(kMaxTile, sel_cap(epi) / k);
     if (batched) {
         for (int qt : {8, 16, 32})
-            for (int bpc : {4, 6, 8})
+            for (int bpc : epi ? std::initializer_list<int>{6, 7, 8} : std::initializer_list<int>{4, 6, 8})
                 if (qt <= qmax || qt == 16) v.push_back(Shape{std::min(qt, qmax), bpc});
     } else {
         for (int qt : {1, 2, 4, 8, 16, 32})
@@ -741,8 +744,8 @@ static std::vector<Shape> shape_candidates(int k, bool batched) {
     return u;
 }
 
-static Shape default_shape(int k, bool batched) {
-    return batched ? Shape{std::min(kMaxTile, kSelCap / k), 6} : Shape{std::min(4, kSelCap / k), 0};
+static Shape default_shape(int k, bool batched, bool epi) {
+    return batched ? Shape{std::min(kMaxTile, sel_cap(epi) / k), epi ? 7 : 6} : Shape{std::min(4, sel_cap(epi) / k), 0};
 }
 
 static bool autotune_enabled() {
@@ -1052,11 +1055,11 @@ static int launch_match_job(cashash_ctx* c, MatchJob& J, ScratchArea* sa = nullp
         tune = !sa && hit == c->tuned.end() && autotune_enabled() && n_pairs > 0;
         if (hit != c->tuned.end())
             cands.push_back(
-                Shape{std::max(1, std::min({hit->second.qt, kMaxTile, kSelCap / c->cfg.k})), hit->second.bpc});
+                Shape{std::max(1, std::min({hit->second.qt, kMaxTile, sel_cap(J.epi) / c->cfg.k})), hit->second.bpc});
         else if (tune)
-            cands = shape_candidates(c->cfg.k, batched);
+            cands = shape_candidates(c->cfg.k, batched, J.epi);
         else
-            cands.push_back(default_shape(c->cfg.k, batched));
+            cands.push_back(default_shape(c->cfg.k, batched, J.epi));
         for (const Shape& sh : cands)
             if (std::find(qts.begin(), qts.end(), sh.qt) == qts.end()) qts.push_back(sh.qt);
         firsts.resize(qts.size());

@@ -16,6 +16,12 @@ constexpr int kOffStride = 257;    // bucket offsets per table (256 keys + end)
 constexpr int kMaxK = 64;
 constexpr int kListCap = 512;      // per-wave LDS candidate list (u32 keys); reused for tile distances
 constexpr int kSelCap = 384;       // per-wave LDS list of a query tile's kept candidates
+// The band kernel's shorter lists: more than kRegCap = 256 band survivors
+// take its fallback path, and its tiles keep at most 320 candidates (32
+// queries at k = 10, fewer queries for larger k).  Less LDS per block, so that
+// seven blocks fit a compute unit.
+constexpr int kListCapEpi = 320;
+constexpr int kSelCapEpi = 320;
 // A query's candidate keys are held in NS 64-wide register slots (NS = 4, 6
 // or 8, a template parameter of the matcher); queries with more candidates
 // use the LDS list.  Plain-form pairs run 4 slots up to kLargeTrain train
@@ -78,7 +84,7 @@ struct PairDev {
     double F[9];        // row-major fundamental matrix (epipolar form)
 };
 
-struct Item {           // a tile of consecutive queries of one pair (nq <= kMaxTile, nq * k <= kSelCap)
+struct Item {           // a tile of consecutive queries of one pair (nq <= kMaxTile, nq * k <= kSelCap or kSelCapEpi)
     int32_t pair;
     int32_t q0;
     int32_t nq;

@@ -300,11 +300,12 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
 }
 
 // Resident blocks per CU each instantiation is compiled for (4 waves per
-// block): the register budget that keeps 6 or 5 wavefronts per SIMD.  The
-// band kernel spills a few registers at 6, but the extra wavefront hides more
-// of its keypoint-load latency.
+// block): the register budget that keeps 7, 6 or 5 wavefronts per SIMD.  The
+// band kernel runs 7 (72 registers, a few spilled outside its band pass; its
+// shorter LDS lists let 7 blocks share a CU's LDS): the extra wavefronts hide
+// more of its keypoint-load latency.
 template <bool EPI, int NS>
-constexpr int kMatchMinBlocks = NS == 4 ? 6 : 5;
+constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 7 : 6) : 5;
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
 //  setup    : lane l loads query l's keys and six bucket ranges at once and
@@ -332,13 +333,16 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                                                     int32_t* __restrict__ o_d2,
                                                     unsigned long long* __restrict__ stats) {
     __shared__ __attribute__((aligned(16))) uint32_t s_hist[kWavesPerBlock][256];
-    __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kListCap];
-    __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSelCap];
+    // candidate list and tile list capacities (the band kernel's are shorter)
+    constexpr int kLC = EPI ? kListCapEpi : kListCap;
+    constexpr int kSC = EPI ? kSelCapEpi : kSelCap;
+    __shared__ __attribute__((aligned(16))) uint32_t s_list[kWavesPerBlock][kLC];
+    __shared__ __attribute__((aligned(16))) uint32_t s_sel[kWavesPerBlock][kSC];
     // run words per query, plus the chunk start masks (4- and 6-slot plain
     // kernels)
     // or the epipolar line (band kernel)
     constexpr bool kMask = (NS == 4 || NS == 6) && !EPI;
-    constexpr int kQS = kMask ? 8 + 2 * NS : (EPI ? 16 : 8);
+    constexpr int kQS = kMask ? 8 + 2 * NS : (EPI ? 14 : 8);
     __shared__ __attribute__((aligned(16))) uint32_t s_qtab[kWavesPerBlock][kMaxTile * kQS];
     // arguments needed only when work is grabbed or a tile is finished, kept
     // in LDS rather than in scalar registers (the kernel is short of them)
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                         const uint32_t sl = n_surv + mbcnt64(mk);
                         // a lane's own survival from its compares, not from
                         // its bit of mk (no 64-bit shift and test per lane)
-                        if (in_band && in_run && sl < (uint32_t)kListCap)
+                        if (in_band && in_run && sl < (uint32_t)kLC)
                             list[sl] = ((8u * (uint32_t)t) << 24) | pos;
                         n_surv += (uint32_t)__popcll(mk);
                     }
@@ -647,7 +651,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     }
                 }
                 wave_sync();
-                if (n_surv <= kRegCap && n_surv <= (uint32_t)kListCap) {
+                if (n_surv <= kRegCap && n_surv <= (uint32_t)kLC) {
                     const uint32_t slots = (n_surv + 63u) >> 6;
                     n_slots = slots;
 #pragma unroll
@@ -719,12 +723,12 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                             const uint32_t slot = n_valid + mbcnt64(mk);
                             if (keep) {
                                 atomicAdd(&hist[kv[u] >> 16], 1u);
-                                if (slot < (uint32_t)kListCap) list[slot] = kv[u];
+                                if (slot < (uint32_t)kLC) list[slot] = kv[u];
                             }
                             n_valid += (uint32_t)__popcll(mk);
                         }
                     }
-                    in_regs = n_valid <= kRegCap && n_valid <= (uint32_t)kListCap;
+                    in_regs = n_valid <= kRegCap && n_valid <= (uint32_t)kLC;
                     wave_sync();
                     if (in_regs) {
                         n_slots = (n_valid + 63u) >> 6;
@@ -750,7 +754,7 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
             // when the query starts
             if (lane == 0) qtab[kQS * qi + 7] = kk | (sel_n << 16);
             if (kk == 0) continue;
-            const bool in_list = n_valid <= (uint32_t)kListCap;
+            const bool in_list = n_valid <= (uint32_t)kLC;
             const uint32_t span = in_list ? n_valid : total;
             uint32_t dummy = 0;
             // number of candidate keys in [lo, hi), counted with ballots
@@ -860,11 +864,11 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                 for (int u = 0; u < NS; ++u) {
                     if (kSkipEmpty && (uint32_t)u >= n_slots) break;
                     // exactly kk <= k keys are kept per query and the host sizes
-                    // tiles so that nq * k <= kSelCap: the slot is in range
+                    // tiles so that nq * k <= kSC: the slot is in range
                     const bool keep = kr[u] <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
-                    if (keep && (!EPI || slot < (uint32_t)kSelCap)) sel[slot] = ((uint32_t)qi << 16) | (kr[u] & 0xFFFFu);
+                    if (keep && (!EPI || slot < (uint32_t)kSC)) sel[slot] = ((uint32_t)qi << 16) | (kr[u] & 0xFFFFu);
                     sel_n += (uint32_t)__popcll(mk);
                 }
             } else {
@@ -875,14 +879,14 @@ __global__ __launch_bounds__(256, (kMatchMinBlocks<EPI, NS>)) void match_kernel(
                     const bool keep = key <= tkey;
                     const uint64_t mk = __ballot(keep);
                     const uint32_t slot = sel_n + mbcnt64(mk);
-                    if (keep && slot < (uint32_t)kSelCap) sel[slot] = ((uint32_t)qi << 16) | (key & 0xFFFFu);
+                    if (keep && slot < (uint32_t)kSC) sel[slot] = ((uint32_t)qi << 16) | (key & 0xFFFFu);
                     sel_n += (uint32_t)__popcll(mk);
                 }
             }
             wave_sync();
         }
 #undef COUNT_RANGE
-        if (sel_n > (uint32_t)kSelCap) sel_n = kSelCap;  // cannot happen when nq * k <= kSelCap
+        if (sel_n > (uint32_t)kSC) sel_n = kSC;  // cannot happen when nq * k <= kSC
 
         // ---- Step 4: squared distances of all kept pairs of the tile, 4 lanes per pair
         for (uint32_t p0 = 0; p0 < sel_n; p0 += 32) {

@@ -319,22 +319,25 @@ def test_bound_buffer_lists(mats):
 
 # ------------------------------------------------------------------ epipolar
 
-def test_epipolar_small_set(mats):
-    _say("epipolar 10 images x 3000")
+@pytest.mark.parametrize("k", [10, 33, 64])
+def test_epipolar_small_set(mats, k):
+    """The band kernel's tiles hold at most 320 kept candidates (32 queries
+    at k = 10, 9 at k = 33, 5 at k = 64)."""
+    _say(f"epipolar 10 images x 3000 k={k}")
     w = synth.epipolar_set(seed=6, n_images=10, n_feat=3000, n_points=20000, n_neighbours=4)
     oc, ok = oracle.build_codes(w.images, *mats)
-    exp = oracle.match_pairs(w.images, oc, ok, w.pairs, k=10, kp=w.kp, F=w.F, max_px=4.0)
+    exp = oracle.match_pairs(w.images, oc, ok, w.pairs, k=k, kp=w.kp, F=w.F, max_px=4.0)
     for mode in ("batched", "plain"):
-        m = binding.Matcher(*mats, mode=mode)
+        m = binding.Matcher(*mats, mode=mode, k=k)
         dimgs, codes, keys, _ = _gpu_codes(m, w.images)
         dkp = _dev(w.kp)
         got, st = m.match_pairs_epipolar(dimgs, codes, keys, dkp, w.pairs, w.F, 4.0)
-        _assert_match(got, exp, f"epipolar {mode}")
+        _assert_match(got, exp, f"epipolar {mode} k={k}")
         assert st["union_size"] < st["bucket_entries"]
     # a band wider than any image equals plain matching
-    plain = oracle.match_pairs(w.images, oc, ok, w.pairs, k=10)
+    plain = oracle.match_pairs(w.images, oc, ok, w.pairs, k=k)
     got, _ = m.match_pairs_epipolar(dimgs, codes, keys, dkp, w.pairs, w.F, 1e7)
-    _assert_match(got, plain, "epipolar huge band")
+    _assert_match(got, plain, f"epipolar huge band k={k}")
 
 
 @pytest.mark.parametrize("k", [1, 10])
