@@ -45,10 +45,10 @@ HBM_PEAK_GBS = 8000.0
 # SQ_INSTS_VALU.  Valid only for the matcher sources they were taken on
 # (sha256 over MATCHER_SOURCES, in order); null otherwise.
 MATCHER_SOURCES = ("cashash_match.hip", "cashash_device.h", "cashash_internal.h")
-MEASURED_COUNTERS = {"sources_sha256": "bddd966ccf232fc74d30808b000dcdc2178d343d9d0c01fa0d24c4ea48ce880d",
+MEASURED_COUNTERS = {"sources_sha256": "0626d8f506a995414bcf9a91e016c82361edccdffa95a25744cfbd3f6c0314b0",
                      "workload": "scenes_100x8000_exhaustive_4950pairs",
-                     "fetch_bytes": int(4397832.4 * 1024 * 2), "write_bytes": int(479156.1 * 1024),
-                     "valu_insts": 8436682457}
+                     "fetch_bytes": int(4442402.8 * 1024 * 2), "write_bytes": int(479141.9 * 1024),
+                     "valu_insts": 8436676742}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles (16 lanes per cycle), 2.4 GHz: 614.4 G instructions/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4

@@ -303,9 +303,10 @@ __device__ __forceinline__ void gather_chunks_mask(uint32_t (&kr)[NS], int lane,
 // block): the register budget that keeps 7, 6 or 5 wavefronts per SIMD.  The
 // band kernel runs 7 (72 registers, a few spilled outside its band pass; its
 // shorter LDS lists let 7 blocks share a CU's LDS): the extra wavefronts hide
-// more of its keypoint-load latency.
+// more of its keypoint-load latency.  The 8-slot kernels run 6 (80 registers);
+// the 6-slot ones 5, as their 28.8 KB of LDS per block allows.
 template <bool EPI, int NS>
-constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 7 : 6) : 5;
+constexpr int kMatchMinBlocks = NS == 4 ? (EPI ? 7 : 6) : (NS == 8 ? 6 : 5);
 
 // One wavefront per tile of <= kMaxTile consecutive queries of one pair.
 //  setup    : lane l loads query l's keys and six bucket ranges at once and
