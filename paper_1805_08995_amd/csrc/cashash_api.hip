@@ -1458,19 +1458,24 @@ static int build_codes_host(cashash_ctx* c, const cashash_images* im, uint64_t* 
 // missing blocks are loaded into free slots of three, the next step's new
 // block is prefetched while the current step computes, and each step's
 // outputs come back through pinned memory.
-// Host-memory matching runs a scheduler step's pairs in parts of at most
-// this many queries (12 output bytes each).
-constexpr int64_t kSubQueries = (int64_t)1 << 24;
+// Host-memory matching runs a scheduler step's pairs in parts (12 output
+// bytes per query), so that a part's download and copy-out overlap the next
+// part's kernels.  A part costs a launch and the bucket tables of its train
+// images, so steps before the last use parts of up to 2^25 queries: their
+// tails overlap the next step's parts.  The last step's tail is exposed, so
+// it uses parts of a fifth of its queries, between 2^23 and 2^24.
+constexpr int64_t kPartQueries = (int64_t)1 << 25;
+constexpr int64_t kLastPartMin = (int64_t)1 << 23, kLastPartMax = (int64_t)1 << 24;
 
-// The part size: kSubQueries, or a smaller one from CASHASH_PART_QUERIES (so
-// that small inputs can run as many parts, as tests do).
-static int64_t part_queries() {
+// CASHASH_PART_QUERIES, if set (1 .. 2^27), fixes the part size of every
+// step (small inputs then run as many parts, as tests do); 0 otherwise.
+static int64_t part_queries_env() {
     const char* e = std::getenv("CASHASH_PART_QUERIES");
     if (e && e[0]) {
         const long long v = std::atoll(e);
-        if (v >= 1 && v < kSubQueries) return (int64_t)v;
+        if (v >= 1 && v <= ((int64_t)1 << 27)) return (int64_t)v;
     }
-    return kSubQueries;
+    return 0;
 }
 
 static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* const* codes,
@@ -1542,7 +1547,7 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         return -1;
     };
     c->last_ms = 0.0;
-    const int64_t part_max = part_queries();
+    const int64_t part_env = part_queries_env();
     // a step whose kernels and download are queued; its outputs are copied
     // into the caller's arrays (over the host threads) once the next step is
     // queued behind it
@@ -1597,8 +1602,8 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
         // the step's pairs, grouped by register-slot group (a part of one
         // group is one persistent launch, not up to three) and then by train
         // image (each part builds the bucket tables of its own train images),
-        // in parts of at most kSubQueries queries, so that a part's download
-        // and copy-out overlap the next part's kernels
+        // in parts (sized as above), so that a part's download and copy-out
+        // overlap the next part's kernels
         std::vector<int64_t> ord(S.order.begin() + step.pair_begin, S.order.begin() + step.pair_end);
         auto group = [&](int64_t p) {
             const int n = im->n_feat[J.pair_t[p]];
@@ -1608,6 +1613,13 @@ static int match_host(cashash_ctx* c, const cashash_images* im, const uint64_t* 
             const int gx = group(x), gy = group(y);
             return gx != gy ? gx < gy : J.pair_t[x] < J.pair_t[y];
         });
+        int64_t part_max = part_env;
+        if (!part_max) {
+            int64_t step_q = 0;
+            for (int64_t p : ord) step_q += im->n_feat[J.pair_q[p]];
+            part_max = st + 1 < S.steps.size() ? kPartQueries
+                                                : std::min(kLastPartMax, std::max(kLastPartMin, step_q / 5));
+        }
         for (size_t pb = 0; pb < ord.size();) {
             size_t pe = pb;
             int64_t nq = 0;
