@@ -166,7 +166,7 @@ struct cashash_ctx {
     std::vector<int32_t> chunk_key;
     DevBuf chunk_dev;
     int chunk_ncol = 0, chunk_ntile = 0;
-    DevBuf stage, outbuf[2];  // host-memory mode: resident image slots; per-step outputs (two steps in flight)
+    DevBuf stage, outbuf[2];  // host-memory mode: resident image slots; part outputs (two parts in flight)
     HostPinned pin[2];        // host-memory mode upload staging
     hipEvent_t pin_ev[2] = {nullptr, nullptr};
     int pin_turn = 0;
