@@ -49,6 +49,12 @@ MEASURED_COUNTERS = {"sources_sha256": "0626d8f506a995414bcf9a91e016c82361edccdf
                      "workload": "scenes_100x8000_exhaustive_4950pairs",
                      "fetch_bytes": int(4442402.8 * 1024 * 2), "write_bytes": int(479141.9 * 1024),
                      "valu_insts": 8436676742}
+# The same for one full band-kernel launch on the epipolar workload
+# (profiles/band_kernel_epipolar_500x12000.md).
+EPIPOLAR_COUNTERS = {"sources_sha256": "0626d8f506a995414bcf9a91e016c82361edccdffa95a25744cfbd3f6c0314b0",
+                     "workload": "epipolar_500x12000_15000pairs_band4px",
+                     "fetch_bytes": int(56264521.5 * 1024 * 2), "write_bytes": int(3739488.0 * 1024),
+                     "valu_insts": 30729692054}
 # VALU issue limit: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles (16 lanes per cycle), 2.4 GHz: 614.4 G instructions/s
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
@@ -62,11 +68,31 @@ def matcher_sha256():
     return h.hexdigest()
 
 
-def measured_counters(workload):
-    t = MEASURED_COUNTERS
+def measured_counters(workload, table=None):
+    t = MEASURED_COUNTERS if table is None else table
     if t["sources_sha256"] != matcher_sha256() or workload != t["workload"]:
         return None
     return t
+
+
+def band_roofline(workload, kernel_ms, queries):
+    """The band kernel against VALU issue, with its measured memory traffic
+    (FETCH_SIZE + WRITE_SIZE, copy-scaled: bytes the L2 fetched from or wrote
+    to memory, the MALL included) against the HBM peak; null fields once the
+    matcher sources change."""
+    t = measured_counters(workload, EPIPOLAR_COUNTERS)
+    sec = kernel_ms * 1e-3
+    out = {"bound": "alu", "kernel": "match_kernel<true, 4, true>", "kernel_ms": round(kernel_ms, 4),
+           "unit": "G VALU wave64 instructions/s", "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+           "achieved": None, "frac": None, "traffic": None, "hbm": None}
+    if t is not None:
+        insts = t["valu_insts"]
+        traffic = t["fetch_bytes"] + t["write_bytes"]
+        out.update(achieved=round(insts / sec / 1e9, 1), frac=round(insts / sec / VALU_ISSUE_PEAK, 4),
+                   traffic=traffic, valu_insts_per_launch=insts, valu_insts_per_query=round(insts / queries, 1))
+        out["hbm"] = {"achieved": round(traffic / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def roofline(workload, kernel_ms, stats):
@@ -349,6 +375,7 @@ def epipolar_leg(binding, synth, torch, mats, reps=5):
            "bucket_entries_per_query": round(st["bucket_entries"] / st["queries"], 2),
            "band_survivors_per_query": round(st["union_size"] / st["queries"], 2),
            "matches": int((outs[0] >= 0).sum().item())}
+    res["roofline"] = band_roofline(res["workload"], res["kernel_ms_median"], st["queries"])
     m.close()
     return res
 
