@@ -28,7 +28,9 @@
  * per-query output arrays, are device pointers when cfg.mem ==
  * CASHASH_MEM_DEVICE and host pointers when cfg.mem == CASHASH_MEM_HOST (the
  * library then streams images to the device in blocks it schedules under
- * cfg.device_budget_bytes and copies results back).  The pair list and the
+ * cfg.device_budget_bytes and copies results back; beyond the budget it keeps
+ * two output areas of up to 2^25 queries x 12 bytes, 400 MB each, in device
+ * memory and in pinned host memory).  The pair list and the
  * fundamental matrices are always host memory.  Calls are synchronous: when
  * a call returns, its outputs are complete.  The library keeps no pointer to
  * caller memory after a call returns.  One context per host thread.
