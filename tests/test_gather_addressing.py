@@ -20,6 +20,11 @@ exactly as the kernel computes it, word by word:
 
 Every candidate of random and edge-case run layouts must get its true
 position and table, and every lane past the runs an in-bounds position.
+
+The band kernel reads keypoints run by run instead, in 64-wide chunks whose
+lanes past a run's end read the entries after it: every entry must be tested
+once with its own table, and no read may pass the 64 keypoints kept after the
+last table.
 """
 import numpy as np
 import pytest
@@ -173,3 +178,46 @@ def test_run_words_fit_32_bits():
     """C << 10 stays below 2^32 for the largest image (C <= 6 n)."""
     n = 65535
     assert ((6 * n) << 10) < 2**32
+
+
+def band_pass_reads(lens, b, n):
+    """The band kernel's band pass, as it addresses keypoints: the run of
+    table t starts at entry rb = t*n + b_t; the first 64 entries of every run
+    are read as one chunk (lane l at rb + l), then 64 more at a time while
+    the run lasts (lane l at rb + i0 + l); a lane tests its entry only if
+    i0 + l < the run's length.  Returns every read position and the
+    (position, table) pairs tested."""
+    reads, tested = [], []
+    for t in range(N_TABLES):
+        rb, rl = t * n + b[t], lens[t]
+        i0 = 0
+        while True:
+            for lane in range(64):
+                p = rb + i0 + lane
+                reads.append(p)
+                if i0 + lane < rl:
+                    tested.append((p, t))
+            i0 += 64
+            if i0 >= rl:
+                break
+    return reads, tested
+
+
+def test_band_pass_addressing():
+    """Every bucket entry of the query's six runs is tested once with its own
+    table, and no read goes more than 64 keypoints past the last table: the
+    band call keeps 512 bytes (64 keypoints of 8 bytes) after its tables."""
+    rng = np.random.default_rng(11)
+    for n in (1, 64, 300, 12000, 65535):
+        for lens in layouts(rng, n, 3000):
+            if max(lens) > n:
+                continue
+            b = runs_of(lens, n, rng)
+            pos, tab = truth(lens, b, n)
+            reads, tested = band_pass_reads(lens, b, n)
+            assert min(reads) >= 0 and max(reads) < N_TABLES * n + 64, (n, lens, b)
+            assert sorted(tested) == sorted(zip(pos.tolist(), tab.tolist())), (n, lens, b)
+            # survivors go to the LDS list as (8t << 24) | pos
+            assert N_TABLES * n + 64 < 2**24
+    # the keypoint byte offset (pos << 3) of the largest image fits 32 bits
+    assert ((N_TABLES * 65535 + 64) << 3) < 2**32
