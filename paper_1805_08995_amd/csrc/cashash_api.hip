@@ -97,9 +97,13 @@ struct DevBuf {
 struct HostPinned {
     void* p = nullptr;
     size_t cap = 0;
+    const cashash_ctx* owner = nullptr;  // whose copies may still use the block
     int ensure(size_t n) {
         if (n <= cap && p) return CASHASH_OK;
-        if (p) hipHostFree(p);
+        if (p) {
+            quiesce(owner);  // a copy of an earlier, failed call may still be in flight
+            hipHostFree(p);
+        }
         p = nullptr;
         cap = 0;
         size_t want = std::max<size_t>(n, 4096);
@@ -412,6 +416,10 @@ extern "C" int cashash_create(cashash_ctx** out, const double* r_code, const dou
     cashash_ctx* c = new cashash_ctx();
     c->R64 = std::move(R);
     for (DevBuf* b : dev_bufs(c)) b->owner = c;
+    for (HostPinned* h : {&c->meta_host[0][0], &c->meta_host[0][1], &c->meta_host[1][0], &c->meta_host[1][1],
+                          &c->meta_host[2][0], &c->meta_host[2][1], &c->pin[0], &c->pin[1], &c->pin_out[0],
+                          &c->pin_out[1], &c->pin_small})
+        h->owner = c;
     auto bail = [&](int code) {
         std::string keep = g_err;
         destroy_ctx(c);
