@@ -735,9 +735,13 @@ static std::vector<Shape> shape_candidates(int k, bool batched, bool epi) {
     std::vector<Shape> v;
     const int qmax = std::min(kMaxTile, sel_cap(epi) / k);
     if (batched) {
+        // persistent blocks per CU: around the occupancy each kernel is
+        // compiled for (7 blocks for the band kernel, 6 or 5 for the others)
+        static const int kBpcPlain[3] = {4, 6, 8}, kBpcEpi[3] = {6, 7, 8};
+        const int* bpcs = epi ? kBpcEpi : kBpcPlain;
         for (int qt : {8, 16, 32})
-            for (int bpc : epi ? std::initializer_list<int>{6, 7, 8} : std::initializer_list<int>{4, 6, 8})
-                if (qt <= qmax || qt == 16) v.push_back(Shape{std::min(qt, qmax), bpc});
+            for (int i = 0; i < 3; ++i)
+                if (qt <= qmax || qt == 16) v.push_back(Shape{std::min(qt, qmax), bpcs[i]});
     } else {
         for (int qt : {1, 2, 4, 8, 16, 32})
             if (qt <= qmax) v.push_back(Shape{qt, 0});
