@@ -189,11 +189,11 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
             sq += __shfl_xor(sq, 32);
             base_margin[b] = margin_coef * sqrtf((float)sq) + 0x1p-26f;
         }
-        uint64_t w[TB][3], m[TB][3];
+        // this lane's bits, packed: row 16 rw + 4 g + i of row block k at bit
+        // 16 (k & 1) + 4 rw + i of word k >> 1 (its own g only)
+        uint32_t pw[TB][2], pm[TB][2];
 #pragma unroll
-        for (int b = 0; b < TB; ++b)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) w[b][k] = m[b][k] = 0;
+        for (int b = 0; b < TB; ++b) pw[b][0] = pw[b][1] = pm[b][0] = pm[b][1] = 0u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int n_rt = k < 2 ? 4 : kRowTiles - 8;
@@ -223,23 +223,32 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const ImgDev* __restrict
                         const float M = base_margin[b] + 0x1p-20f * fabsf(bv[i]);
                         const bool nr = !(fabsf(v) > M);
                         const bool bit = !nr && v > 0.f;
-                        const int pos = 16 * rw + 4 * g + i;
-                        w[b][k] |= (uint64_t)bit << pos;
-                        m[b][k] |= (uint64_t)nr << pos;
+                        const int pos = 16 * (k & 1) + 4 * rw + i;
+                        pw[b][k >> 1] |= (uint32_t)bit << pos;
+                        pm[b][k >> 1] |= (uint32_t)nr << pos;
                     }
             }
         }
+        // unpack to rows 16 rw + 4 g + i (g: this lane's row group)
+        auto unpack = [&](uint32_t p16) {
+            uint64_t r = 0;
+#pragma unroll
+            for (int rw = 0; rw < 4; ++rw) r |= (uint64_t)((p16 >> (4 * rw)) & 0xFu) << (16 * rw + 4 * g);
+            return r;
+        };
 #pragma unroll
         for (int b = 0; b < TB; ++b) {
+            uint64_t w[3] = {unpack(pw[b][0] & 0xFFFFu), unpack(pw[b][0] >> 16), unpack(pw[b][1])};
+            uint64_t m[3] = {unpack(pm[b][0] & 0xFFFFu), unpack(pm[b][0] >> 16), unpack(pm[b][1])};
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                w[b][k] |= __shfl_xor(w[b][k], 16);
-                w[b][k] |= __shfl_xor(w[b][k], 32);
-                m[b][k] |= __shfl_xor(m[b][k], 16);
-                m[b][k] |= __shfl_xor(m[b][k], 32);
+                w[k] |= __shfl_xor(w[k], 16);
+                w[k] |= __shfl_xor(w[k], 32);
+                m[k] |= __shfl_xor(m[k], 16);
+                m[k] |= __shfl_xor(m[k], 32);
             }
-            store_code(outs[tc[b].img], tc[b].img, tc[b].r0 + n, g == 0 && live[b], w[b][0], w[b][1], w[b][2],
-                       m[b][0], m[b][1], m[b][2], seg, cnt);
+            store_code(outs[tc[b].img], tc[b].img, tc[b].r0 + n, g == 0 && live[b], w[0], w[1], w[2], m[0], m[1],
+                       m[2], seg, cnt);
         }
     }
     if (lane == 0) seg_count[wave] = cnt;
