@@ -115,6 +115,13 @@ def test_uneven_full_size_device_and_streamed(uneven):
          f"{sth2['ms_match']:.0f} ms")
     assert sth2["image_loads"] > len(w.images)
     _check_pairs(g, w, goth, "uneven host")
+    del goth
+    # the whole set resident: one scheduler step matched in many parts
+    mr = binding.Matcher(*mats, mode="batched", mem="host")
+    gotr, str_ = mr.match_pairs(w.images, hcodes, hkeys, w.pairs)
+    _say(f"host mode, resident: {str_['image_loads']} image loads, {str_['ms_match']:.0f} ms")
+    assert str_["image_loads"] == len(w.images)
+    _check_pairs(g, w, gotr, "uneven host resident")
 
 
 def test_epipolar_full_size():
